@@ -1,0 +1,230 @@
+"""FP64 CPU oracle for the binned spin pair correlation (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and
+nothing here imports the product package.
+
+The arithmetic lives in ``sdc_oracle.c`` (plain C, FP64, OpenMP over the
+origin site i); this module loads it with ctypes and converts numpy arrays.
+Each function states the paper passage it follows (arXiv 2308.07487):
+
+- ``binned_corr``      Eq. (4) unsubtracted, summed over alpha as in Eq. (3),
+                       cast per lag as the GEMM of Sec. 3.2 and binned by a
+                       key computed from positions (the role of Q in Eq. (6)).
+- ``finalize``         per-bin normalisation, site sum (Sec. 1: summing the
+                       correlation over all sites) and the windowed time
+                       transform of Sec. 2.2.
+- ``ll_rk4``           Eq. (2) with the exchange term of Eq. (1), RK4 without
+                       renormalisation (Sec. 3.1).
+- ``philox`` / ``init_state``  Philox4x32-10 (Salmon et al., SC'11) seeded
+                       initial states.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sdc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libsdc_oracle.so")
+
+SC, BCC, RADIAL = 0, 1, 2
+_ERR = {1: "invalid argument", 3: "out of memory"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O3, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+            "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm",
+        ])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, i32, f32, f64, u64, u32 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                         ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32)
+        L.oracle_n_bins.argtypes = [P, i64, ctypes.c_int, P, i32, f32, P]
+        L.oracle_pair_keys.argtypes = [P, i64, ctypes.c_int, P, i32, f32, P, P, i64, P]
+        L.oracle_binned_corr.argtypes = [P, i64, ctypes.c_int, P, i32, f32, P, i64, i32, i32,
+                                         P, i32, i64, i64, P, P, ctypes.c_int]
+        L.oracle_binned_corr_select.argtypes = [P, i64, ctypes.c_int, P, i32, f32, P, i64, i32,
+                                                i32, P, i32, P, i32, P, P, ctypes.c_int]
+        L.oracle_self_corr.argtypes = [P, i64, i64, i32, i32, P, i32, P]
+        L.oracle_dft.argtypes = [P, i32, P]
+        L.oracle_finalize.argtypes = [P, P, i64, i32, i64, P, P, P, P, P, P, P]
+        L.oracle_ll_rk4.argtypes = [i64, P, P, P, P, f64, i64, P]
+        L.oracle_philox.argtypes = [u64, u32, i64, i64, P]
+        L.oracle_init_state.argtypes = [u64, i64, ctypes.c_int, f64, P]
+        L.oracle_philox_block.argtypes = [P, P, P]
+        for name in ("oracle_n_bins", "oracle_pair_keys", "oracle_binned_corr",
+                     "oracle_binned_corr_select", "oracle_self_corr", "oracle_dft",
+                     "oracle_finalize", "oracle_ll_rk4", "oracle_philox", "oracle_init_state",
+                     "oracle_philox_block"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what}: {_ERR.get(rc, rc)}")
+
+
+def _spec(kind, cells, n_shells, r_max):
+    cells = np.ascontiguousarray(cells if cells is not None else (0, 0, 0), dtype=np.int32)
+    return int(kind), cells, int(n_shells), float(r_max)
+
+
+def n_bins(pos, kind, cells=None, n_shells=0, r_max=0.0):
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    kind, cells, n_shells, r_max = _spec(kind, cells, n_shells, r_max)
+    out = ctypes.c_int64(0)
+    _check(lib().oracle_n_bins(_ptr(pos), pos.shape[0], kind, _ptr(cells), n_shells, r_max,
+                               ctypes.byref(out)), "n_bins")
+    return int(out.value)
+
+
+def pair_keys(pos, kind, pi, pj, cells=None, n_shells=0, r_max=0.0):
+    """Bin of each ordered pair (pi[p] = origin site, pj[p] = later site)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    kind, cells, n_shells, r_max = _spec(kind, cells, n_shells, r_max)
+    pi = np.ascontiguousarray(pi, dtype=np.int64)
+    pj = np.ascontiguousarray(pj, dtype=np.int64)
+    out = np.zeros(pi.shape[0], dtype=np.int64)
+    _check(lib().oracle_pair_keys(_ptr(pos), pos.shape[0], kind, _ptr(cells), n_shells, r_max,
+                                  _ptr(pi), _ptr(pj), pi.shape[0], _ptr(out)), "pair_keys")
+    return out
+
+
+def binned_corr(pos, frames, kind, n_origins, lags, stride=1, cells=None, n_shells=0,
+                r_max=0.0, rows=None, counts=True, n_threads=0):
+    """Raw binned sums H[l][b] (FP64) and pair counts (uint64).
+
+    H[l][b] = sum over ordered pairs (i, j) with key(i, j) = b of
+              sum_{o < n_origins} S_i(o*stride) . S_j(o*stride + lags[l]).
+    ``rows`` = (i_begin, i_end) restricts the origin sites (partial sums).
+    """
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    frames = np.ascontiguousarray(frames, dtype=np.float32)
+    n = pos.shape[0]
+    assert frames.ndim == 3 and frames.shape[1] == n and frames.shape[2] == 3
+    kind_, cells_, ns, rm = _spec(kind, cells, n_shells, r_max)
+    nb = n_bins(pos, kind, cells, n_shells, r_max)
+    lags = np.ascontiguousarray(lags, dtype=np.int32)
+    i0, i1 = (0, n) if rows is None else rows
+    H = np.zeros((lags.shape[0], nb), dtype=np.float64)
+    C = np.zeros(nb, dtype=np.uint64) if counts else None
+    _check(lib().oracle_binned_corr(_ptr(pos), n, kind_, _ptr(cells_), ns, rm, _ptr(frames),
+                                    frames.shape[0], int(n_origins), int(stride), _ptr(lags),
+                                    lags.shape[0], int(i0), int(i1), _ptr(H), _ptr(C),
+                                    int(n_threads)), "binned_corr")
+    return H, C
+
+
+def binned_corr_select(pos, frames, kind, n_origins, lags, bins, stride=1, cells=None,
+                       n_shells=0, r_max=0.0, n_threads=0):
+    """H restricted to selected bins: returns (H_sel[n_lags][n_sel], counts_sel)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    frames = np.ascontiguousarray(frames, dtype=np.float32)
+    kind_, cells_, ns, rm = _spec(kind, cells, n_shells, r_max)
+    lags = np.ascontiguousarray(lags, dtype=np.int32)
+    bins = np.ascontiguousarray(bins, dtype=np.int64)
+    H = np.zeros((lags.shape[0], bins.shape[0]), dtype=np.float64)
+    C = np.zeros(bins.shape[0], dtype=np.uint64)
+    _check(lib().oracle_binned_corr_select(_ptr(pos), pos.shape[0], kind_, _ptr(cells_), ns, rm,
+                                           _ptr(frames), frames.shape[0], int(n_origins),
+                                           int(stride), _ptr(lags), lags.shape[0], _ptr(bins),
+                                           bins.shape[0], _ptr(H), _ptr(C), int(n_threads)),
+           "binned_corr_select")
+    return H, C
+
+
+def self_corr(frames, n_origins, lags, stride=1):
+    """sum_o sum_i S_i(o*stride) . S_i(o*stride + lag), per lag (FP64)."""
+    frames = np.ascontiguousarray(frames, dtype=np.float32)
+    lags = np.ascontiguousarray(lags, dtype=np.int32)
+    out = np.zeros(lags.shape[0], dtype=np.float64)
+    _check(lib().oracle_self_corr(_ptr(frames), frames.shape[1], frames.shape[0], int(n_origins),
+                                  int(stride), _ptr(lags), lags.shape[0], _ptr(out)), "self_corr")
+    return out
+
+
+def dft(x):
+    """Half-Hann windowed DFT, complex128."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros((x.shape[0], 2), dtype=np.float64)
+    _check(lib().oracle_dft(_ptr(x), x.shape[0], _ptr(out)), "dft")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def finalize(H, counts, n_sites, n_org, self_raw):
+    """C[l][b], Csum[l], Cself[l], Ssum[k] (complex), Sself[k] (complex)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    nl, nb = H.shape
+    n_org = np.ascontiguousarray(np.broadcast_to(np.asarray(n_org, dtype=np.float64), (nl,)))
+    self_raw = np.ascontiguousarray(self_raw, dtype=np.float64)
+    C = np.zeros_like(H)
+    Cs = np.zeros(nl)
+    Cf = np.zeros(nl)
+    Ss = np.zeros((nl, 2))
+    Sf = np.zeros((nl, 2))
+    _check(lib().oracle_finalize(_ptr(H), _ptr(counts), nb, nl, int(n_sites), _ptr(n_org),
+                                 _ptr(self_raw), _ptr(C), _ptr(Cs), _ptr(Cf), _ptr(Ss), _ptr(Sf)),
+           "finalize")
+    return C, Cs, Cf, Ss[:, 0] + 1j * Ss[:, 1], Sf[:, 0] + 1j * Sf[:, 1]
+
+
+def ll_rk4(row, col, J, init, dt, n_frames):
+    """RK4 frames [n_frames][n][3] (FP64) for dS_i/dt = (sum_j J_ij S_j) x S_i."""
+    row = np.ascontiguousarray(row, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    init = np.ascontiguousarray(init, dtype=np.float32)
+    n = init.shape[0]
+    out = np.zeros((int(n_frames), n, 3), dtype=np.float64)
+    _check(lib().oracle_ll_rk4(n, _ptr(row), _ptr(col), _ptr(J), _ptr(init), float(dt),
+                               int(n_frames), _ptr(out)), "ll_rk4")
+    return out
+
+
+def philox(seed, draw, idx0, n_blocks):
+    out = np.zeros((int(n_blocks), 4), dtype=np.uint32)
+    _check(lib().oracle_philox(int(seed), int(draw), int(idx0), int(n_blocks), _ptr(out)), "philox")
+    return out
+
+
+def philox_block(ctr, key):
+    """One raw Philox4x32-10 block for a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _check(lib().oracle_philox_block(_ptr(c), _ptr(k), _ptr(out)), "philox_block")
+    return out
+
+
+def init_state(seed, n, mode=0, sigma=0.0):
+    out = np.zeros((int(n), 3), dtype=np.float64)
+    _check(lib().oracle_init_state(int(seed), int(n), int(mode), float(sigma), _ptr(out)),
+           "init_state")
+    return out

@@ -1,0 +1,491 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test ties one oracle function to a closed form, an invariant, a numpy
+library routine, brute force on tiny inputs or a hand-worked fixture, chosen
+so that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them.  Paper: arXiv 2308.07487.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2308_07487_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, *v = line.split()
+        rows.setdefault(k, []).append([float(x) for x in v])
+    return rows
+
+
+# --------------------------------------------------------------------------
+# fixtures from the definition, worked by hand
+# --------------------------------------------------------------------------
+
+def test_hand_worked_sc(orc):
+    g = _read_golden("hand_sc2.txt")
+    pos = np.array(g["pos"], dtype=np.float32)
+    frames = np.array([np.reshape(g[f"frame{f}"][0], (2, 3)) for f in range(3)], dtype=np.float32)
+    H, cnt = orc.binned_corr(pos, frames, orc.SC, 2, [0, 1], cells=(2, 1, 1))
+    np.testing.assert_array_equal(H[0], g["H_lag0"][0])
+    np.testing.assert_array_equal(H[1], g["H_lag1"][0])
+    np.testing.assert_array_equal(cnt, np.array(g["counts"][0], dtype=np.uint64))
+    self_raw = orc.self_corr(frames, 2, [0, 1])
+    C, Cs, Cf, Ss, Sf = orc.finalize(H, cnt, 2, 2.0, self_raw)
+    np.testing.assert_allclose(C[0], g["C_lag0"][0], atol=1e-15)
+    np.testing.assert_allclose(C[1], g["C_lag1"][0], atol=1e-15)
+    np.testing.assert_allclose(Cs, g["Csum"][0], atol=1e-15)
+    np.testing.assert_allclose(Cf, g["Cself"][0], atol=1e-15)
+    np.testing.assert_allclose(Ss.real, g["Ssum_re"][0], atol=1e-15)
+    np.testing.assert_allclose(Sf.real, g["Sself_re"][0], atol=1e-15)
+    np.testing.assert_allclose(Ss.imag, 0.0, atol=1e-15)
+
+
+def test_hand_worked_radial(orc):
+    g = _read_golden("hand_radial3.txt")
+    pos = np.array(g["pos"], dtype=np.float32)
+    ns, rm = int(g["n_shells"][0][0]), g["r_max"][0][0]
+    frames = inputs.random_unit_frames(1, 3, seed=1)
+    H, cnt = orc.binned_corr(pos, frames, orc.RADIAL, 1, [0], n_shells=ns, r_max=rm)
+    np.testing.assert_array_equal(cnt, np.array(g["counts"][0], dtype=np.uint64))
+
+
+# --------------------------------------------------------------------------
+# brute force on tiny inputs (independent Python evaluation, math.fsum)
+# --------------------------------------------------------------------------
+
+def _brute(pos, frames, key, n_bins, n_o, s, lags):
+    n = pos.shape[0]
+    f64 = frames.astype(np.float64)
+    H = np.zeros((len(lags), n_bins))
+    cnt = np.zeros(n_bins, dtype=np.uint64)
+    for i in range(n):
+        for j in range(n):
+            b = key(i, j)
+            cnt[b] += 1
+            for li, t in enumerate(lags):
+                terms = [f64[o * s, i, a] * f64[o * s + t, j, a] for o in range(n_o) for a in range(3)]
+                H[li, b] += math.fsum(terms)
+    return H, cnt
+
+
+def test_brute_force_sc(orc):
+    L = (2, 3, 4)
+    pos = inputs.sc_positions(L)
+    pos, _, _ = inputs.permute_sites(pos, np.zeros((1, pos.shape[0], 3), np.float32), seed=3)
+    n = pos.shape[0]
+    frames = inputs.random_unit_frames(9, n, seed=7)
+    lags = [0, 1, 3]
+    ip = np.rint(pos).astype(int)
+
+    def key(i, j):
+        d = (ip[j] - ip[i]) % np.array(L)
+        return (d[0] * L[1] + d[1]) * L[2] + d[2]
+
+    Hb, cb = _brute(pos, frames, key, n, 3, 2, lags)
+    H, c = orc.binned_corr(pos, frames, orc.SC, 3, lags, stride=2, cells=L)
+    np.testing.assert_allclose(H, Hb, rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(c, cb)
+
+
+def test_brute_force_bcc_doubled_coordinates(orc):
+    """bcc key through doubled integer coordinates D = 2r: the displacement
+    D_j - D_i (mod 2L) has components of one parity p; the bin is
+    2 * sc_index(floor(D / 2)) + p.  A different formulation from the
+    oracle's sublattice-shift rule."""
+    L = (2, 2, 3)
+    pos = inputs.bcc_positions(L)
+    n = pos.shape[0]
+    frames = inputs.random_unit_frames(6, n, seed=11)
+    D = np.rint(2 * pos).astype(int)
+    L2 = 2 * np.array(L)
+
+    def key(i, j):
+        d = (D[j] - D[i]) % L2
+        p = d[0] % 2
+        assert d[1] % 2 == p and d[2] % 2 == p
+        k = d // 2
+        return 2 * ((k[0] * L[1] + k[1]) * L[2] + k[2]) + p
+
+    Hb, cb = _brute(pos, frames, key, n, 2, 1, [0, 2, 4])
+    H, c = orc.binned_corr(pos, frames, orc.BCC, 2, [0, 2, 4], cells=L)
+    np.testing.assert_allclose(H, Hb, rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(c, cb)
+
+
+def test_brute_force_radial_float32_key(orc):
+    """Radial key evaluated with numpy float32 arithmetic (no fused ops)."""
+    n = 40
+    pos = inputs.ball_positions(n, 3.0, seed=5)
+    ns, rm = 37, 6.0
+    frames = inputs.random_unit_frames(5, n, seed=6)
+    w = rm / ns
+    e2 = np.array([np.float32((k * w) ** 2) for k in range(ns)], dtype=np.float32)
+
+    def key(i, j):
+        d = (pos[j] - pos[i]).astype(np.float32)
+        d2 = np.float32(np.float32(d[0] * d[0]) + np.float32(d[1] * d[1]))
+        d2 = np.float32(d2 + np.float32(d[2] * d[2]))
+        return int(np.searchsorted(e2, d2, side="right") - 1)
+
+    Hb, cb = _brute(pos, frames, key, ns, 3, 1, [0, 2])
+    H, c = orc.binned_corr(pos, frames, orc.RADIAL, 3, [0, 2], n_shells=ns, r_max=rm)
+    np.testing.assert_allclose(H, Hb, rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(c, cb)
+    assert int(c.sum()) == n * n
+
+
+# --------------------------------------------------------------------------
+# closed forms and invariants
+# --------------------------------------------------------------------------
+
+def test_unit_spins_c00_is_one(orc):
+    L = (4, 3, 5)
+    pos = inputs.sc_positions(L)
+    fr = inputs.axis_frames(6, pos.shape[0], seed=2)
+    H, c = orc.binned_corr(pos, fr, orc.SC, 4, [0, 1], cells=L)
+    C, *_ = orc.finalize(H, c, pos.shape[0], 4.0, np.zeros(2))
+    assert C[0, 0] == 1.0
+    assert abs(C[1, 0] - 1.0) > 1e-3  # lag 1 decorrelates random frames
+    fr = inputs.random_unit_frames(6, pos.shape[0], seed=2)
+    H, c = orc.binned_corr(pos, fr, orc.SC, 4, [0], cells=L)
+    C, *_ = orc.finalize(H, c, pos.shape[0], 4.0, np.zeros(1))
+    assert abs(C[0, 0] - 1.0) < 1e-6  # fp32 rounding of the unit length
+
+
+def test_sum_identity_total_magnetisation(orc):
+    """sum_b H(b,t) = sum_o M(t_o) . M(t_o + t), M = sum_i S_i."""
+    L = (3, 4, 2)
+    pos = inputs.bcc_positions(L)
+    fr = inputs.random_unit_frames(10, pos.shape[0], seed=4)
+    lags = [0, 1, 5]
+    H, _ = orc.binned_corr(pos, fr, orc.BCC, 3, lags, stride=2, cells=L)
+    M = fr.astype(np.float64).sum(axis=1)
+    for li, t in enumerate(lags):
+        ref = sum(M[2 * o] @ M[2 * o + t] for o in range(3))
+        assert abs(H[li].sum() - ref) < 1e-11
+
+
+def test_static_ferromagnet_is_one_everywhere(orc):
+    for kind, pos, extra in [
+        (orc.SC, inputs.sc_positions((3, 4, 5)), dict(cells=(3, 4, 5))),
+        (orc.BCC, inputs.bcc_positions((2, 3, 2)), dict(cells=(2, 3, 2))),
+        (orc.RADIAL, inputs.ball_positions(50, 2.5, 1), dict(n_shells=16, r_max=5.0)),
+    ]:
+        fr = inputs.static_frames(7, pos.shape[0], (0.3, -0.55, 0.7))
+        H, c = orc.binned_corr(pos, fr, kind, 3, [0, 2, 4], **extra)
+        C, Cs, Cf, *_ = orc.finalize(H, c, pos.shape[0], 3.0, orc.self_corr(fr, 3, [0, 2, 4]))
+        occupied = c > 0
+        np.testing.assert_allclose(C[:, occupied], 1.0, atol=2e-7)  # fp32 input rounding of |s|^2
+        np.testing.assert_array_equal(C[:, ~occupied], 0.0)
+        np.testing.assert_allclose(Cs, Cf * pos.shape[0], rtol=1e-6)
+
+
+@pytest.mark.parametrize("theta", [np.pi / 2, 0.8])
+def test_planted_spiral_closed_form(orc, theta):
+    """C(d, t) = sin^2(th) cos(q.d - w t) + cos^2(th) for every bin."""
+    L = (6, 4, 5)
+    pos = inputs.sc_positions(L)
+    q = 2 * np.pi * np.array([1, 1, 2]) / np.array(L)
+    omega, dt = 1.3, 0.1
+    fr = inputs.spiral_frames(pos, q, theta, omega, 12, dt)
+    lags = [0, 1, 4]
+    H, c = orc.binned_corr(pos, fr, orc.SC, 5, lags, cells=L)
+    C, *_ = orc.finalize(H, c, pos.shape[0], 5.0, np.zeros(3))
+    b = np.arange(pos.shape[0])
+    d = np.stack([b // (L[1] * L[2]), (b // L[2]) % L[1], b % L[2]], axis=1)
+    for li, t in enumerate(lags):
+        ref = np.sin(theta) ** 2 * np.cos(d @ q - omega * t * dt) + np.cos(theta) ** 2
+        np.testing.assert_allclose(C[li], ref, atol=2e-6)
+
+
+def test_counts_closed_forms(orc):
+    pos = inputs.sc_positions((3, 5, 4))
+    _, c = orc.binned_corr(pos, inputs.random_unit_frames(1, 60, 0), orc.SC, 1, [0], cells=(3, 5, 4))
+    assert np.all(c == 60)
+    pos = inputs.bcc_positions((2, 3, 3))
+    _, c = orc.binned_corr(pos, inputs.random_unit_frames(1, 36, 0), orc.BCC, 1, [0], cells=(2, 3, 3))
+    assert np.all(c == 36)
+    pos = inputs.ball_positions(70, 3.0, 9)
+    _, c = orc.binned_corr(pos, inputs.random_unit_frames(1, 70, 0), orc.RADIAL, 1, [0],
+                           n_shells=40, r_max=6.0)
+    assert int(c.sum()) == 70 * 70 and int(c[0]) >= 70
+    # each unordered pair counted twice (i <-> j), self pairs once
+    assert (int(c.sum()) - 70) % 2 == 0
+
+
+def test_lag_zero_displacement_symmetry(orc):
+    """H(d, 0) = H(-d, 0)."""
+    L = (4, 5, 3)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(4, 60, seed=8)
+    H, _ = orc.binned_corr(pos, fr, orc.SC, 4, [0], cells=L)
+    b = np.arange(60)
+    d = np.stack([b // 15, (b // 3) % 5, b % 3], axis=1)
+    nd = (-d) % np.array(L)
+    bm = (nd[:, 0] * 5 + nd[:, 1]) * 3 + nd[:, 2]
+    np.testing.assert_allclose(H[0], H[0][bm], rtol=1e-13)
+
+
+def test_fft_cross_correlation_sc(orc):
+    """Periodic lattice: H(d,t) = sum_o sum_a IFFT(conj(F[S_a(t_o)]) F[S_a(t_o+t)])(d)."""
+    L = (6, 5, 4)
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    fr = inputs.random_unit_frames(8, n, seed=12)
+    lags = [0, 2, 5]
+    H, _ = orc.binned_corr(pos, fr, orc.SC, 3, lags, cells=L)
+    g = fr.astype(np.float64).reshape(8, *L, 3)
+    for li, t in enumerate(lags):
+        acc = np.zeros(L)
+        for o in range(3):
+            for a in range(3):
+                A = np.fft.fftn(g[o, ..., a])
+                B = np.fft.fftn(g[o + t, ..., a])
+                acc += np.fft.ifftn(np.conj(A) * B).real
+        np.testing.assert_allclose(H[li], acc.reshape(-1), atol=1e-11)
+
+
+def test_fft_cross_correlation_bcc(orc):
+    """bcc as two interleaved cubic grids: parity 0 bins collect same-sublattice
+    correlations; parity 1 bins collect corr(S0, S1)(k) + corr(S1, S0)(k + 1)."""
+    L = (4, 3, 4)
+    pos = inputs.bcc_positions(L)
+    n = pos.shape[0]
+    fr = inputs.random_unit_frames(5, n, seed=13).astype(np.float64)
+    H, _ = orc.binned_corr(pos, fr.astype(np.float32), orc.BCC, 2, [1], cells=L)
+    g = fr.reshape(5, *L, 2, 3)  # positions were written corner, centre alternating
+
+    def corr(a, b):
+        return np.fft.ifftn(np.conj(np.fft.fftn(a)) * np.fft.fftn(b)).real
+
+    h0 = np.zeros(L)
+    h1 = np.zeros(L)
+    for o in range(2):
+        for a in range(3):
+            s0, s1 = g[o, ..., 0, a], g[o, ..., 1, a]
+            t0, t1 = g[o + 1, ..., 0, a], g[o + 1, ..., 1, a]
+            h0 += corr(s0, t0) + corr(s1, t1)
+            h1 += corr(s0, t1) + np.roll(corr(s1, t0), shift=(-1, -1, -1), axis=(0, 1, 2))
+    np.testing.assert_allclose(H[0][0::2], h0.reshape(-1), atol=1e-11)
+    np.testing.assert_allclose(H[0][1::2], h1.reshape(-1), atol=1e-11)
+
+
+def test_structure_factor_link_eq3(orc):
+    """Eq. (3) link: the direct double sum over sites of exp(-i q.(r_j - r_i))
+    S_i(t_o).S_j(t_o+t) equals the binned sum weighted by exp(-i q.d_b)."""
+    L = (4, 4, 3)
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    fr = inputs.random_unit_frames(6, n, seed=21)
+    H, _ = orc.binned_corr(pos, fr, orc.SC, 3, [2], cells=L)
+    b = np.arange(n)
+    d = np.stack([b // 12, (b // 3) % 4, b % 3], axis=1)
+    f = fr.astype(np.float64)
+    for m in [(0, 0, 0), (1, 0, 0), (1, 2, 1), (3, 1, 2)]:
+        q = 2 * np.pi * np.array(m) / np.array(L)
+        ph = np.exp(-1j * (pos @ q))
+        direct = 0.0
+        for o in range(3):
+            A = f[o]          # origin spins S_i(t_o)
+            B = f[o + 2]      # later spins S_j(t_o + t)
+            # sum_ij e^{-iq(r_j - r_i)} A_i . B_j
+            direct += np.sum((np.conj(ph)[:, None] * A).sum(axis=0) * (ph[:, None] * B).sum(axis=0))
+        binned = np.sum(np.exp(-1j * (d @ q)) * H[0])
+        assert abs(direct - binned) < 1e-10
+
+
+def test_dft_matches_numpy_fft(orc):
+    rng = np.random.default_rng(3)
+    for m in (1, 2, 7, 64):
+        x = rng.standard_normal(m)
+        w = 0.5 * (1 + np.cos(np.pi * np.arange(m) / m))
+        np.testing.assert_allclose(orc.dft(x), np.fft.fft(w * x), atol=1e-12)
+    x = np.ones(16)
+    w = 0.5 * (1 + np.cos(np.pi * np.arange(16) / 16))
+    assert abs(orc.dft(x)[0] - w.sum()) < 1e-13
+
+
+def test_site_permutation_invariance(orc):
+    L = (3, 3, 4)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(5, 36, seed=31)
+    H1, c1 = orc.binned_corr(pos, fr, orc.SC, 3, [0, 2], cells=L)
+    p2, f2, _ = inputs.permute_sites(pos, fr, seed=32)
+    H2, c2 = orc.binned_corr(p2, f2, orc.SC, 3, [0, 2], cells=L)
+    np.testing.assert_allclose(H1, H2, rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(c1, c2)
+
+
+def test_linearity_over_origins(orc):
+    """Origins [0,2) then [2,5) (by shifting the frames) add up to origins [0,5)."""
+    L = (3, 2, 4)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(9, 24, seed=41)
+    Ha, _ = orc.binned_corr(pos, fr, orc.SC, 2, [0, 3], cells=L)
+    Hb, _ = orc.binned_corr(pos, fr[2:], orc.SC, 3, [0, 3], cells=L)
+    Hc, _ = orc.binned_corr(pos, fr, orc.SC, 5, [0, 3], cells=L)
+    np.testing.assert_allclose(Ha + Hb, Hc, rtol=1e-13, atol=1e-13)
+
+
+def test_row_partition_adds_up(orc):
+    L = (4, 2, 3)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(4, 24, seed=42)
+    Hf, cf = orc.binned_corr(pos, fr, orc.SC, 2, [1], cells=L)
+    Ha, ca = orc.binned_corr(pos, fr, orc.SC, 2, [1], cells=L, rows=(0, 10))
+    Hb, cb = orc.binned_corr(pos, fr, orc.SC, 2, [1], cells=L, rows=(10, 24))
+    np.testing.assert_allclose(Ha + Hb, Hf, rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(ca + cb, cf)
+
+
+def test_select_matches_full(orc):
+    pos = inputs.ball_positions(60, 3.0, seed=50)
+    fr = inputs.random_unit_frames(6, 60, seed=51)
+    kw = dict(n_shells=30, r_max=6.0)
+    H, c = orc.binned_corr(pos, fr, orc.RADIAL, 3, [0, 2], **kw)
+    bins = np.array([0, 3, 7, 29])
+    Hs, cs = orc.binned_corr_select(pos, fr, orc.RADIAL, 3, [0, 2], bins, **kw)
+    np.testing.assert_allclose(Hs, H[:, bins], rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(cs, c[bins])
+
+
+def test_nan_propagates(orc):
+    L = (2, 2, 2)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(4, 8, seed=1)
+    fr[1, 3, 0] = np.nan
+    H, _ = orc.binned_corr(pos, fr, orc.SC, 2, [0], cells=L)
+    assert np.isnan(H).any()
+
+
+def test_invalid_inputs_rejected(orc):
+    pos = inputs.sc_positions((2, 2, 2))
+    fr = inputs.random_unit_frames(3, 8, seed=1)
+    with pytest.raises(ValueError):
+        orc.binned_corr(pos, fr, orc.SC, 2, [2], cells=(2, 2, 2))   # needs 4 frames
+    with pytest.raises(ValueError):
+        orc.binned_corr(pos + 0.3, fr, orc.SC, 1, [0], cells=(2, 2, 2))  # off-lattice
+    bad = pos.copy()
+    bad[1] = bad[0]
+    with pytest.raises(ValueError):
+        orc.binned_corr(bad, fr, orc.SC, 1, [0], cells=(2, 2, 2))  # duplicate site
+
+
+# --------------------------------------------------------------------------
+# Landau-Lifshitz RK4 (Eq. 2) and seeded initial states
+# --------------------------------------------------------------------------
+
+def _nn_csr(pos, L, kind, J):
+    """Nearest-neighbour bonds built from coordinates (numpy, independent)."""
+    n = pos.shape[0]
+    if kind == "sc":
+        c = np.rint(pos).astype(int)
+        index = {tuple(x): i for i, x in enumerate(c)}
+        deltas = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+        mod = np.array(L)
+        cols = [[index[tuple((c[i] + np.array(d)) % mod)] for d in deltas] for i in range(n)]
+    else:
+        D = np.rint(2 * pos).astype(int)
+        index = {tuple(x): i for i, x in enumerate(D)}
+        mod = 2 * np.array(L)
+        deltas = [(sx, sy, sz) for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
+        cols = [[index[tuple((D[i] + np.array(d)) % mod)] for d in deltas] for i in range(n)]
+    z = len(cols[0])
+    row = np.arange(n + 1, dtype=np.int64) * z
+    col = np.array(cols, dtype=np.int32).reshape(-1)
+    return row, col, np.full(col.shape[0], float(J)), z
+
+
+@pytest.mark.parametrize("kind", ["sc", "bcc"])
+def test_rk4_spiral_is_exact_solution(orc, kind):
+    """A spin wave S = (sin th cos phi, sin th sin phi, cos th), phi = q.r - w t,
+    solves Eq. (2) exactly with w = J cos th (gamma_q - z), gamma_q the
+    neighbour sum of cos(q.delta)."""
+    L = (6, 6, 4)
+    pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+    J, theta, dt, nf = 1.0, 0.7, 0.01, 201
+    q = 2 * np.pi * np.array([1, 2, 1]) / np.array(L)
+    row, col, Jv, z = _nn_csr(pos, L, kind, J)
+    if kind == "sc":
+        gamma = 2 * (np.cos(q[0]) + np.cos(q[1]) + np.cos(q[2]))
+    else:
+        gamma = 8 * np.cos(q[0] / 2) * np.cos(q[1] / 2) * np.cos(q[2] / 2)
+    omega = J * np.cos(theta) * (gamma - z)
+    exact = inputs.spiral_frames(pos, q, theta, omega, nf, dt).astype(np.float64)
+    init = inputs.spiral_frames(pos, q, theta, omega, 1, dt)[0]
+    out = orc.ll_rk4(row, col, Jv, init, dt, nf)
+    # fp32 rounding of the start (~6e-8) plus RK4 truncation
+    assert np.abs(out - exact).max() < 3e-7
+    # a wrong sign of the precession or of gamma would be off by O(1)
+    wrong = inputs.spiral_frames(pos, q, theta, -omega, nf, dt).astype(np.float64)
+    assert np.abs(out - wrong).max() > 1e-2
+
+
+def test_rk4_conserves_magnetisation(orc):
+    L = (4, 4, 4)
+    pos = inputs.sc_positions(L)
+    row, col, Jv, _ = _nn_csr(pos, L, "sc", -1.0)
+    init = inputs.random_unit_frames(1, 64, seed=3)[0]
+    out = orc.ll_rk4(row, col, Jv, init, 0.01, 300)
+    M = out.sum(axis=1)
+    assert np.abs(M - M[0]).max() < 1e-12
+    # and the dynamics is not trivial
+    assert np.abs(out[-1] - out[0]).max() > 1e-2
+
+
+def test_rk4_single_bond_precession(orc):
+    """Two spins, one bond: each precesses about the conserved total M with
+    angular speed J|M| (closed form)."""
+    row = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    J = 0.8
+    Jv = np.array([J, J])
+    s0 = np.array([1.0, 0.0, 0.0])
+    s1 = np.array([0.0, 0.6, 0.8])
+    init = np.stack([s0, s1]).astype(np.float32)
+    dt, nf = 0.01, 301
+    out = orc.ll_rk4(row, col, Jv, init, dt, nf)
+    S0 = init[0].astype(np.float64)
+    M = init.astype(np.float64).sum(axis=0)
+    m = M / np.linalg.norm(M)
+    w = J * np.linalg.norm(M)
+    for f in (0, 100, 300):
+        t = f * dt
+        # dS0/dt = J S1 x S0 = J (M - S0) x S0 = J M x S0: rotation about m by +w t
+        par = m * (m @ S0)
+        perp = S0 - par
+        ref = par + perp * np.cos(w * t) + np.cross(m, perp) * np.sin(w * t)
+        assert np.abs(out[f, 0] - ref).max() < 1e-8
+
+
+def test_philox_known_answers(orc):
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        np.testing.assert_array_equal(orc.philox_block(w[0:4], w[4:6]), np.array(w[6:10], np.uint32))
+
+
+def test_init_state_distribution(orc):
+    s = orc.init_state(0x5DC00002, 20000, mode=0)
+    np.testing.assert_allclose(np.linalg.norm(s, axis=1), 1.0, atol=1e-12)
+    assert np.abs(s.mean(axis=0)).max() < 0.03
+    # z is uniform on [-1, 1]: variance 1/3
+    assert abs(s[:, 2].var() - 1 / 3) < 0.02
+    p = orc.init_state(0x5DC00001, 20000, mode=1, sigma=0.3)
+    np.testing.assert_allclose(np.linalg.norm(p, axis=1), 1.0, atol=1e-12)
+    ang = np.arccos(np.clip(p[:, 2], -1, 1))
+    # |v| is Rayleigh(sigma): mean sigma sqrt(pi/2)
+    assert abs(ang.mean() - 0.3 * np.sqrt(np.pi / 2)) < 0.01
+    # the generator is counter-based: site i does not depend on n
+    np.testing.assert_array_equal(orc.init_state(7, 10)[:5], orc.init_state(7, 5))

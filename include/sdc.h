@@ -1,0 +1,255 @@
+/*
+ * sdc.h -- C ABI of the fused, binned spin pair-correlation library (gfx950).
+ *
+ * The library computes, on one AMD Instinct MI355X, the space- and
+ * time-displaced spin pair correlation
+ *
+ *     C(b, t) = < S_i(t0) . S_j(t0 + t) >   over ordered pairs (i, j) in bin b
+ *
+ * (Eq. (4) of arXiv 2308.07487 without the mean subtraction, summed over the
+ * components alpha as in Eq. (3), averaged over time origins t0 of one
+ * trajectory instead of Monte Carlo realizations), binned by the displacement
+ * of site j (at the later time) relative to site i (at the origin).  Each lag
+ * is the dense product of the N x 3*n_origins spin matrices (Sec. 3.2); the
+ * bin key and the histogram are fused into the product's epilogue so the
+ * N x N result never reaches memory (Sec. 3.3-3.4, Fig. 2, Eq. (6)).
+ *
+ * Conventions for every entry point:
+ *  - Return codes only; nothing throws or aborts across this ABI.
+ *  - Argument and state errors are detected before any GPU work is queued.
+ *  - GPU failures map to SDC_ERR_HIP; faults of queued work surface at the
+ *    next synchronising call (sdc_finalize, sdc_plan_raw).
+ *  - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *  - sdc_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef SDC_H
+#define SDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SDC_OK = 0,
+    SDC_ERR_INVALID_ARG = 1,  /* a pointer, size or spec field is invalid     */
+    SDC_ERR_STATE = 2,        /* call not allowed in the plan's current state */
+    SDC_ERR_OOM = 3,          /* host or device allocation failed             */
+    SDC_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed   */
+    SDC_ERR_UNSUPPORTED = 5,  /* valid request outside what this build does   */
+    SDC_ERR_NO_DEVICE = 6     /* no usable gfx950 device                      */
+} sdc_status;
+
+/* Contraction precision of the per-lag product.  Accumulation is always
+ * FP32 inside the matrix cores, the per-workgroup histograms and the global
+ * bins are FP64.
+ *  FP32        : plain FP32 MFMA (v_mfma_f32_32x32x2_f32).
+ *  SPLIT_BF16  : x = hi + lo, hi = bf16(x), lo = bf16(x - hi); the product is
+ *                hi*hi + hi*lo + lo*hi on BF16 MFMA (three products).
+ *  SPLIT_FP16  : the same split with FP16 parts (about 22 significant bits).
+ *  For both splits the omitted lo*lo product is added exactly (FP64) for the
+ *  i = j pairs, where it would otherwise bias C at zero displacement; off the
+ *  diagonal it is left out (unbiased rounding noise, <= 2^-16 (BF16) or
+ *  2^-22 (FP16) of |S_i||S_j| per term). */
+typedef enum {
+    SDC_PREC_FP32 = 0,
+    SDC_PREC_SPLIT_BF16 = 1,
+    SDC_PREC_SPLIT_FP16 = 2
+} sdc_precision;
+
+/* Bin kinds.
+ *  PERIODIC_SC  : simple-cubic lattice, lattice constant 1, cells[0..2] cells
+ *                 per axis, one site per cell at the integer point.  Bin =
+ *                 displacement (r_j - r_i) mod cells, index
+ *                 b = (kx*cells[1] + ky)*cells[2] + kz; n_bins = N.
+ *  PERIODIC_BCC : body-centred cubic, sites n and n + (1/2,1/2,1/2).  Bin =
+ *                 (k, p) with k = (n_j - n_i - [beta_j < beta_i](1,1,1)) mod
+ *                 cells and p = (beta_j - beta_i) mod 2; b = 2*sc_index(k) + p;
+ *                 n_bins = N = 2*cells^3.
+ *  RADIAL       : arbitrary positions, no periodicity.  n_shells shells of
+ *                 width w = r_max / n_shells.  d2 = ((dx*dx + dy*dy) + dz*dz)
+ *                 in FP32 with dx = fp32(x_j - x_i), no fused multiply-add;
+ *                 shell = largest k with E2[k] <= d2, E2[k] = fp32((k*w)^2)
+ *                 evaluated in FP64 and rounded; distances beyond the last
+ *                 edge fall in the last shell. */
+typedef enum {
+    SDC_BINS_PERIODIC_SC = 0,
+    SDC_BINS_PERIODIC_BCC = 1,
+    SDC_BINS_RADIAL = 2
+} sdc_bin_kind;
+
+typedef struct {
+    int32_t kind;      /* sdc_bin_kind                                      */
+    int32_t cells[3];  /* periodic kinds: cells per axis (each >= 1)        */
+    int32_t n_shells;  /* radial: number of shells, 1..1024                 */
+    float r_max;       /* radial: outer edge of the last shell, > 0         */
+} sdc_bin_spec;
+
+typedef struct {
+    int32_t n_origins;     /* time origins per accumulate call, >= 1         */
+    int32_t n_lags;        /* lags 0..n_lags-1, in frames, >= 1              */
+    int32_t origin_stride; /* frames between origins s, >= 1 (origin o uses  */
+                           /* frame o*s; lag t pairs it with frame o*s + t)  */
+    int32_t precision;     /* sdc_precision                                  */
+    int32_t flags;         /* 0 or SDC_FLAG_TIMING                           */
+} sdc_corr_spec;
+
+/* flags: record HIP events around each kernel of sdc_accumulate (on the
+ * caller's stream) so sdc_plan_timings can report per-kernel durations. */
+#define SDC_FLAG_TIMING 1
+
+typedef struct sdc_plan sdc_plan;
+
+/*
+ * Create a plan for one sample (Sec. 3.2: the spin matrices; Sec. 3.4 and
+ * Eq. (6): values computed from positions inside the epilogue).
+ *  positions_host : [n_sites][3] fp32, host, copied; periodic kinds need
+ *                   lattice points within 1e-3 (bcc: 2r within 2e-3) with
+ *                   every site of the box exactly once.
+ *  device         : HIP device ordinal; the plan's memory lives there.
+ *  out            : receives the plan (owned by the library until destroy).
+ * Builds the tile layout, copies tables to the device and computes the exact
+ * per-bin pair counts (integer kernel), synchronously.
+ * Errors: INVALID_ARG (bad pointer/spec/positions), UNSUPPORTED, OOM,
+ *         NO_DEVICE, HIP.
+ */
+sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites,
+                           const sdc_bin_spec* bins, const sdc_corr_spec* corr,
+                           int device, sdc_plan** out);
+
+/* Number of bins of the plan.  Errors: INVALID_ARG. */
+sdc_status sdc_plan_n_bins(const sdc_plan* plan, int64_t* n_bins);
+
+/*
+ * Add one trajectory's contribution (Eq. (4) unsubtracted, Eq. (3) alpha sum,
+ * averaged over origins; the GEMM of Sec. 3.2 with the fused epilogue of
+ * Sec. 3.3-3.4).  For every selected lag t and origin o < n_origins:
+ *     H[t][key(i,j)] += S_i(o*s) . S_j(o*s + t)   for all ordered pairs.
+ *  spins_dev  : [n_frames][n_sites][3] fp32 in device memory of the plan's
+ *               device, site order as in positions_host; read-only; must stay
+ *               valid until the stream reaches this work.
+ *  n_frames   : >= (n_origins - 1)*s + max_selected_lag + 1.
+ *  lags_host  : host array of n_lags_sel distinct lags in [0, n_lags), or
+ *               NULL for all lags (then n_lags_sel is ignored).
+ *  stream     : hipStream_t; everything is queued on it, nothing waits.
+ * Repeated calls add; the per-lag origin totals add too.  Graph-capturable.
+ * Errors: INVALID_ARG, STATE (plan failed earlier), HIP.
+ */
+sdc_status sdc_accumulate(sdc_plan* plan, const float* spins_dev, int64_t n_frames,
+                          const int32_t* lags_host, int32_t n_lags_sel, void* stream);
+
+/*
+ * Normalise and transform (Sec. 2.2: temporal transform with a window;
+ * Sec. 1: summing the correlation over all sites), in FP64 on the GPU, then
+ * copy to host buffers and synchronise the stream.  Any output may be NULL.
+ *  C_host      : [n_lags][n_bins]  H / (n_org[t] * count[b]), 0 if either is 0
+ *  counts_host : [n_bins] exact ordered-pair counts (uint64)
+ *  Csum_host   : [n_lags]  sum_b H[t][b] / (N * n_org[t])
+ *  Cself_host  : [n_lags]  sum_o sum_i S_i(o s).S_i(o s + t) / (N * n_org[t])
+ *  Ssum_host   : [n_lags][2] (re, im) of sum_t w_t Csum(t) exp(-2 pi i k t / n_lags)
+ *  Sself_host  : [n_lags][2] same for Cself; w_t = (1 + cos(pi t / n_lags)) / 2
+ * May be called repeatedly; it does not reset the accumulation.
+ * Errors: INVALID_ARG, STATE, HIP (including faults of earlier queued work).
+ */
+sdc_status sdc_finalize(sdc_plan* plan, double* C_host, uint64_t* counts_host,
+                        double* Csum_host, double* Cself_host, double* Ssum_host,
+                        double* Sself_host, void* stream);
+
+/*
+ * Raw accumulated state (for exact comparisons and checkpointing): H
+ * [n_lags][n_bins] FP64, per-lag origin totals [n_lags] FP64, raw self sums
+ * [n_lags] FP64.  Any output may be NULL.  Synchronises the stream.
+ * Errors: INVALID_ARG, STATE, HIP.
+ */
+sdc_status sdc_plan_raw(sdc_plan* plan, double* H_host, double* n_org_host,
+                        double* self_host, void* stream);
+
+/* Replace the accumulated state with one saved by sdc_plan_raw (resume).
+ * Synchronises the stream.  Errors: INVALID_ARG, STATE, HIP. */
+sdc_status sdc_plan_load_raw(sdc_plan* plan, const double* H_host,
+                             const double* n_org_host, const double* self_host,
+                             void* stream);
+
+/* Per-kernel durations (milliseconds) of the most recent sdc_accumulate of a
+ * plan created with SDC_FLAG_TIMING: ms[0] pack, ms[1] self term, ms[2] fused
+ * product + epilogue.  Waits for those events.  Errors: INVALID_ARG, STATE
+ * (no timed accumulate yet or flag not set), HIP. */
+sdc_status sdc_plan_timings(sdc_plan* plan, double* ms);
+
+/* Zero the accumulated state (counts are kept).  Queued on the stream. */
+sdc_status sdc_plan_reset(sdc_plan* plan, void* stream);
+
+/* Free the plan and its device memory (waits for the device).  NULL is a
+ * no-op.  The pointer is invalid afterwards. */
+sdc_status sdc_plan_destroy(sdc_plan* plan);
+
+/* Static description of a status code. */
+const char* sdc_status_string(sdc_status s);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* sdc_last_error(void);
+
+/*
+ * Host-only check of the tile layout (no device needed): the bin of every
+ * ordered pair as the fused kernel's epilogue maps it (tile pair, window
+ * coordinate, window-to-bin map), written to keys_out[i*n_sites + j].
+ * Sizes up to n_sites = 4096.  Errors: INVALID_ARG, UNSUPPORTED, OOM.
+ */
+sdc_status sdc_layout_keys(const float* positions_host, int64_t n_sites,
+                           const sdc_bin_spec* bins, int64_t* keys_out);
+
+/* ---------------------------------------------------------------------- */
+/* Trajectory generator: Landau-Lifshitz RK4 (Eq. (2), Sec. 3.1)           */
+/* ---------------------------------------------------------------------- */
+
+typedef enum {
+    SDC_COUPLING_NN_UNIFORM = 0,   /* J on every nearest-neighbour bond      */
+    SDC_COUPLING_NN_RANDOM_SIGN = 1, /* +-|J| per bond, Philox sign          */
+    SDC_COUPLING_EXP_CUTOFF = 2    /* J*exp(-r) for d2 <= r_cut^2 (FP32 rule) */
+} sdc_coupling;
+
+typedef enum {
+    SDC_INIT_UNIFORM = 0,      /* uniform unit vectors (Philox)               */
+    SDC_INIT_PERTURBED_Z = 1,  /* z-aligned + Gaussian tangent of width sigma */
+    SDC_INIT_GIVEN = 2         /* copy init_dev                               */
+} sdc_init;
+
+typedef struct {
+    int32_t kind;       /* sdc_bin_kind of the positions: SC/BCC periodic     */
+                        /* lattices (nearest neighbours) or RADIAL (open)     */
+    int32_t cells[3];   /* periodic box                                       */
+    int32_t coupling;   /* sdc_coupling                                       */
+    float r_cut;        /* EXP_CUTOFF: cutoff radius                          */
+    double J;           /* exchange; J > 0 antiferromagnetic (Eq. (1))        */
+    double dt;          /* RK4 step; one frame per step                       */
+    int32_t init;       /* sdc_init                                           */
+    int32_t pad0;
+    double sigma;       /* PERTURBED_Z tangent width (radians)                */
+    uint64_t seed;      /* Philox4x32-10 key                                  */
+    const float* init_dev; /* GIVEN: [n_sites][3] fp32 device memory          */
+} sdc_traj_spec;
+
+/*
+ * Integrate dS_i/dt = (sum_j J_ij S_j) x S_i with classical RK4 (no
+ * renormalisation) in FP32 and write frames [n_frames][n_sites][3] fp32 into
+ * frames_dev (frame 0 = initial state, frame f = after f steps).
+ *  positions_host : [n_sites][3] fp32 host; neighbour bonds come from them.
+ * Initial states: Philox4x32-10 with key = seed, counter = (site low 32 bits,
+ * 0, site high 32 bits, 0); u = (word >> 8) * 2^-24; UNIFORM uses z = 2u0 - 1,
+ * phi = 2 pi u1; PERTURBED_Z uses Box-Muller normals (g0, g1) from (u0, u1),
+ * v = sigma (g0, g1), S = (sin|v| v/|v|, cos|v|).  Random bond signs use
+ * counter (min(i,j), max(i,j), 1, 0): sign = -1 if the first word is odd.
+ * Synchronises the stream before returning (host-built bond tables).
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP, NO_DEVICE.
+ */
+sdc_status sdc_traj_generate(const float* positions_host, int64_t n_sites,
+                             const sdc_traj_spec* spec, float* frames_dev,
+                             int64_t n_frames, int device, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDC_H */

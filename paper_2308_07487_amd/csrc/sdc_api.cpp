@@ -1,0 +1,640 @@
+// C ABI of the sdc library: argument validation, plan state, device memory,
+// and the sequence of kernels behind each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sdc_internal.h"
+
+using sdc::KGroup;
+using sdc::KPair;
+using sdc::KStream;
+using sdc::Layout;
+
+namespace {
+
+thread_local std::string g_err;
+
+sdc_status set_err(sdc_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+sdc_status hip_err(int e, const char* what) {
+    return set_err(SDC_ERR_HIP, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
+}
+
+#define SDC_HIP(call, what)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_err((int)e_, what); \
+    } while (0)
+
+// Checks that a usable gfx950 device exists and makes it current.
+sdc_status use_device(int device) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+        return set_err(SDC_ERR_NO_DEVICE, "no HIP device");
+    if (device < 0 || device >= count) return set_err(SDC_ERR_INVALID_ARG, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    SDC_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_err(SDC_ERR_NO_DEVICE, std::string("device is not gfx950: ") + prop.gcnArchName);
+    SDC_HIP(hipSetDevice(device), "hipSetDevice");
+    return SDC_OK;
+}
+
+template <class T>
+sdc_status dalloc(T** p, size_t count, std::vector<void*>* owned) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(SDC_ERR_OOM, "hipMalloc failed");
+    }
+    owned->push_back(*p);
+    return SDC_OK;
+}
+
+// Groups of lags for one lag selection: lag t = s*u + phase, grouped by
+// (phase, 16-aligned block of u), with a mask of the selected members.
+std::vector<KGroup> make_groups(const std::vector<int>& lags, int s) {
+    std::map<std::pair<int, int>, int> mask;
+    for (int t : lags) {
+        const int ph = t % s, u = t / s, u0 = (u / sdc::kLagGroup) * sdc::kLagGroup;
+        mask[{ph, u0}] |= 1 << (u - u0);
+    }
+    std::vector<KGroup> g;
+    for (auto& kv : mask) g.push_back(KGroup{kv.first.first, kv.first.second, kv.second, 0});
+    return g;
+}
+
+}  // namespace
+
+sdc_status sdc::set_error(sdc_status s, const std::string& msg) { return set_err(s, msg); }
+
+struct LagSel {
+    KGroup* d_groups = nullptr;
+    int n_groups = 0;
+    int32_t* d_lags = nullptr;
+    int n_sel = 0;
+    int max_lag = 0;
+    std::vector<int> lags;
+};
+
+struct sdc_plan {
+    int device = 0;
+    sdc_bin_spec bins{};
+    sdc_corr_spec corr{};
+    Layout lay;
+    int n_c = 0, O8 = 0, F8 = 0;
+    int64_t t_req = 0;
+    std::vector<void*> owned;
+    int32_t* d_perm = nullptr;
+    int32_t* d_gtab = nullptr;
+    float* d_pos4 = nullptr;
+    float* d_e2 = nullptr;
+    KPair* d_pairs = nullptr;
+    KStream* d_streams = nullptr;
+    unsigned long long* d_counts = nullptr;
+    double* d_H = nullptr;
+    double* d_self = nullptr;
+    double* d_norg = nullptr;
+    double* d_C = nullptr;
+    double* d_fin = nullptr;  // csum, cself, ssum[2], sself[2]
+    void* d_A = nullptr;
+    void* d_B = nullptr;
+    size_t bytes_A = 0, bytes_B = 0;
+    std::vector<double> n_org;
+    std::map<std::vector<int>, LagSel> sels;
+    bool failed = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
+
+    ~sdc_plan() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+sdc_status get_sel(sdc_plan* p, const int32_t* lags_host, int32_t n_sel, const LagSel** out) {
+    std::vector<int> lags;
+    if (!lags_host) {
+        lags.resize(p->corr.n_lags);
+        for (int t = 0; t < p->corr.n_lags; ++t) lags[t] = t;
+    } else {
+        if (n_sel < 1 || n_sel > p->corr.n_lags)
+            return set_err(SDC_ERR_INVALID_ARG, "n_lags_sel must be in [1, n_lags]");
+        lags.assign(lags_host, lags_host + n_sel);
+        std::vector<int> sorted = lags;
+        std::sort(sorted.begin(), sorted.end());
+        for (size_t k = 0; k < sorted.size(); ++k) {
+            if (sorted[k] < 0 || sorted[k] >= p->corr.n_lags)
+                return set_err(SDC_ERR_INVALID_ARG, "lag out of [0, n_lags)");
+            if (k > 0 && sorted[k] == sorted[k - 1]) return set_err(SDC_ERR_INVALID_ARG, "duplicate lag");
+        }
+        lags = sorted;
+    }
+    auto it = p->sels.find(lags);
+    if (it != p->sels.end()) {
+        *out = &it->second;
+        return SDC_OK;
+    }
+    LagSel sel;
+    sel.lags = lags;
+    sel.n_sel = (int)lags.size();
+    sel.max_lag = lags.back();
+    std::vector<KGroup> g = make_groups(lags, p->corr.origin_stride);
+    sel.n_groups = (int)g.size();
+    sdc_status s = dalloc(&sel.d_groups, g.size(), &p->owned);
+    if (s != SDC_OK) return s;
+    s = dalloc(&sel.d_lags, lags.size(), &p->owned);
+    if (s != SDC_OK) return s;
+    // one-time upload per distinct selection; later calls reuse it and stay
+    // asynchronous (and capturable)
+    SDC_HIP(hipMemcpy(sel.d_groups, g.data(), g.size() * sizeof(KGroup), hipMemcpyHostToDevice), "upload groups");
+    SDC_HIP(hipMemcpy(sel.d_lags, lags.data(), lags.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload lags");
+    auto res = p->sels.emplace(lags, sel);
+    *out = &res.first->second;
+    return SDC_OK;
+}
+
+sdc_status check_specs(const sdc_bin_spec* bins, const sdc_corr_spec* corr) {
+    if (!bins || !corr) return set_err(SDC_ERR_INVALID_ARG, "null spec");
+    if (corr->n_origins < 1 || corr->n_origins > 4096)
+        return set_err(SDC_ERR_INVALID_ARG, "n_origins must be in [1, 4096]");
+    if (corr->n_lags < 1 || corr->n_lags > 1024) return set_err(SDC_ERR_INVALID_ARG, "n_lags must be in [1, 1024]");
+    if (corr->origin_stride < 1 || corr->origin_stride > 64)
+        return set_err(SDC_ERR_INVALID_ARG, "origin_stride must be in [1, 64]");
+    if (corr->precision < SDC_PREC_FP32 || corr->precision > SDC_PREC_SPLIT_FP16)
+        return set_err(SDC_ERR_INVALID_ARG, "unknown precision");
+    if ((corr->flags & ~SDC_FLAG_TIMING) != 0) return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
+    if (bins->kind < SDC_BINS_PERIODIC_SC || bins->kind > SDC_BINS_RADIAL)
+        return set_err(SDC_ERR_INVALID_ARG, "unknown bin kind");
+    return SDC_OK;
+}
+
+sdc_status plan_usable(const sdc_plan* p) {
+    if (!p) return set_err(SDC_ERR_INVALID_ARG, "null plan");
+    if (p->failed) return set_err(SDC_ERR_STATE, "plan is unusable after an earlier device failure");
+    return SDC_OK;
+}
+
+sdc_status fused_args(const sdc_plan* p, const LagSel& sel, sdc::FusedArgs* a) {
+    const Layout& L = p->lay;
+    std::memset(a, 0, sizeof(*a));
+    a->A = p->d_A;
+    a->B = p->d_B;
+    a->n_pad = L.n_pad;
+    a->O8 = p->O8;
+    a->F8 = p->F8;
+    a->n_c = p->n_c;
+    a->phase_stride = (int64_t)3 * p->F8 * L.n_pad;
+    a->pairs = p->d_pairs;
+    a->streams = p->d_streams;
+    a->n_streams = (int)L.streams.size();
+    a->groups = sel.d_groups;
+    a->n_groups = sel.n_groups;
+    a->gtab = p->d_gtab;
+    a->pos4 = p->d_pos4;
+    a->e2 = p->d_e2;
+    a->n_shells = L.n_shells;
+    a->inv_w = L.n_shells ? (float)((double)L.n_shells / (double)p->bins.r_max) : 0.0f;
+    a->kind = L.kind;
+    a->L0 = L.L[0];
+    a->L1 = L.L[1];
+    a->L2 = L.L[2];
+    a->W1 = L.W[1];
+    a->W2 = L.W[2];
+    a->win = L.win;
+    a->H = p->d_H;
+    a->n_bins = L.n_bins;
+    a->stride = p->corr.origin_stride;
+    a->precision = p->corr.precision;
+    if ((int64_t)a->n_groups * a->n_streams > (int64_t)INT32_MAX / 2)
+        return set_err(SDC_ERR_UNSUPPORTED, "too many fused tasks");
+    return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sdc_status_string(sdc_status s) {
+    switch (s) {
+        case SDC_OK: return "ok";
+        case SDC_ERR_INVALID_ARG: return "invalid argument";
+        case SDC_ERR_STATE: return "invalid state";
+        case SDC_ERR_OOM: return "out of memory";
+        case SDC_ERR_HIP: return "HIP error";
+        case SDC_ERR_UNSUPPORTED: return "unsupported";
+        case SDC_ERR_NO_DEVICE: return "no usable device";
+    }
+    return "unknown status";
+}
+
+const char* sdc_last_error(void) { return g_err.c_str(); }
+
+sdc_status sdc_layout_keys(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
+                           int64_t* keys_out) {
+    g_err.clear();
+    if (!positions_host || !bins || !keys_out) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    if (n_sites < 1 || n_sites > 4096) return set_err(SDC_ERR_INVALID_ARG, "n_sites must be in [1, 4096]");
+    Layout lay;
+    std::string err;
+    sdc_status s;
+    try {
+        s = sdc::build_layout(positions_host, n_sites, bins, &lay, &err);
+    } catch (const std::bad_alloc&) {
+        return set_err(SDC_ERR_OOM, "host allocation failed");
+    }
+    if (s != SDC_OK) return set_err(s, err);
+    const int64_t n = n_sites;
+    std::vector<uint8_t> seen((size_t)(n * n), 0);
+    const float inv_w = lay.n_shells ? (float)((double)lay.n_shells / (double)bins->r_max) : 0.0f;
+    for (const KStream& st : lay.streams) {
+        for (int p = st.p0; p < st.p1; ++p) {
+            const KPair& pr = lay.pairs[p];
+            for (int a = 0; a < sdc::kTile; ++a)
+                for (int b = 0; b < sdc::kTile; ++b) {
+                    const int64_t pi = (int64_t)pr.ti * sdc::kTile + a;
+                    const int64_t pj = (int64_t)pr.tj * sdc::kTile + b;
+                    const int32_t i = lay.perm[pi], j = lay.perm[pj];
+                    if (lay.kind != SDC_BINS_RADIAL) {
+                        // every slot, padding included, must land inside the window:
+                        // the kernels bin padded slots too (with zero spins)
+                        const int w = lay.gtab[pj] - lay.gtab[pi] + pr.shift;
+                        if (w < 0 || w >= lay.win)
+                            return set_err(SDC_ERR_INVALID_ARG, "window coordinate out of range");
+                    }
+                    if (i < 0 || j < 0) continue;
+                    int64_t key;
+                    if (lay.kind == SDC_BINS_RADIAL) {
+                        const float* ri = &lay.pos4[4 * pi];
+                        const float* rj = &lay.pos4[4 * pj];
+                        key = sdc::shell_of(sdc::dist2_f32(ri[0], ri[1], ri[2], rj[0], rj[1], rj[2]),
+                                            lay.e2.data(), lay.n_shells, inv_w);
+                    } else {
+                        const int w = lay.gtab[pj] - lay.gtab[pi] + pr.shift;
+                        if (w < 0 || w >= lay.win) return set_err(SDC_ERR_INVALID_ARG, "window coordinate out of range");
+                        key = sdc::window_bin(lay, st, w);
+                    }
+                    const int64_t x = (int64_t)i * n + j;
+                    if (seen[x]) return set_err(SDC_ERR_INVALID_ARG, "pair visited twice");
+                    seen[x] = 1;
+                    keys_out[x] = key;
+                }
+        }
+    }
+    for (uint8_t v : seen)
+        if (!v) return set_err(SDC_ERR_INVALID_ARG, "pair not visited");
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
+                           const sdc_corr_spec* corr, int device, sdc_plan** out) {
+    g_err.clear();
+    if (!out) return set_err(SDC_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (!positions_host) return set_err(SDC_ERR_INVALID_ARG, "null positions");
+    sdc_status s = check_specs(bins, corr);
+    if (s != SDC_OK) return s;
+    sdc_plan* p = nullptr;
+    try {
+        p = new sdc_plan();
+        p->bins = *bins;
+        p->corr = *corr;
+        std::string err;
+        s = sdc::build_layout(positions_host, n_sites, bins, &p->lay, &err);
+        if (s != SDC_OK) {
+            delete p;
+            return set_err(s, err);
+        }
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return set_err(SDC_ERR_OOM, "host allocation failed");
+    }
+    s = use_device(device);
+    if (s != SDC_OK) {
+        delete p;
+        return s;
+    }
+    p->device = device;
+    const Layout& L = p->lay;
+    const int sstr = corr->origin_stride;
+    p->n_c = (corr->n_origins + sdc::kKStep - 1) / sdc::kKStep;
+    p->O8 = 2 * p->n_c;
+    const int u_max = (corr->n_lags - 1) / sstr;
+    const int u0_max = (u_max / sdc::kLagGroup) * sdc::kLagGroup;
+    p->F8 = 2 * p->n_c + u0_max / 8 + 2;
+    p->t_req = (int64_t)(corr->n_origins - 1) * sstr + corr->n_lags;
+    p->bytes_A = (size_t)3 * p->O8 * L.n_pad * 32;
+    p->bytes_B = (size_t)sstr * 3 * p->F8 * L.n_pad * 32;
+    p->n_org.assign(corr->n_lags, 0.0);
+    if (sdc::fused_lds_bytes(L.win) > 160 * 1024) {
+        delete p;
+        return set_err(SDC_ERR_UNSUPPORTED, "histogram window does not fit in LDS");
+    }
+
+#define TRY(x)                  \
+    do {                        \
+        sdc_status s_ = (x);    \
+        if (s_ != SDC_OK) {     \
+            delete p;           \
+            return s_;          \
+        }                       \
+    } while (0)
+#define TRYHIP(call, what)                              \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) {                         \
+            delete p;                                   \
+            return hip_err((int)e_, what);              \
+        }                                               \
+    } while (0)
+
+    TRY(dalloc(&p->d_perm, L.n_pad, &p->owned));
+    TRY(dalloc(&p->d_gtab, L.n_pad, &p->owned));
+    TRY(dalloc(&p->d_pos4, L.pos4.size(), &p->owned));
+    TRY(dalloc(&p->d_e2, L.e2.size(), &p->owned));
+    TRY(dalloc(&p->d_pairs, L.pairs.size(), &p->owned));
+    TRY(dalloc(&p->d_streams, L.streams.size(), &p->owned));
+    TRY(dalloc(&p->d_counts, (size_t)L.n_bins, &p->owned));
+    TRY(dalloc(&p->d_H, (size_t)corr->n_lags * L.n_bins, &p->owned));
+    TRY(dalloc(&p->d_self, (size_t)corr->n_lags, &p->owned));
+    TRY(dalloc(&p->d_norg, (size_t)corr->n_lags, &p->owned));
+    TRY(dalloc(&p->d_fin, (size_t)6 * corr->n_lags, &p->owned));
+    TRY(dalloc((char**)&p->d_A, p->bytes_A, &p->owned));
+    TRY(dalloc((char**)&p->d_B, p->bytes_B, &p->owned));
+
+    TRYHIP(hipMemcpy(p->d_perm, L.perm.data(), L.n_pad * sizeof(int32_t), hipMemcpyHostToDevice), "upload perm");
+    TRYHIP(hipMemcpy(p->d_gtab, L.gtab.data(), L.n_pad * sizeof(int32_t), hipMemcpyHostToDevice), "upload gtab");
+    if (!L.pos4.empty())
+        TRYHIP(hipMemcpy(p->d_pos4, L.pos4.data(), L.pos4.size() * sizeof(float), hipMemcpyHostToDevice), "upload pos");
+    if (!L.e2.empty())
+        TRYHIP(hipMemcpy(p->d_e2, L.e2.data(), L.e2.size() * sizeof(float), hipMemcpyHostToDevice), "upload edges");
+    TRYHIP(hipMemcpy(p->d_pairs, L.pairs.data(), L.pairs.size() * sizeof(KPair), hipMemcpyHostToDevice), "upload pairs");
+    TRYHIP(hipMemcpy(p->d_streams, L.streams.data(), L.streams.size() * sizeof(KStream), hipMemcpyHostToDevice),
+           "upload streams");
+    if (corr->flags & SDC_FLAG_TIMING)
+        for (int k = 0; k < 4; ++k) TRYHIP(hipEventCreate(&p->ev[k]), "hipEventCreate");
+    TRYHIP(hipMemset(p->d_counts, 0, (size_t)L.n_bins * 8), "zero counts");
+    TRYHIP(hipMemset(p->d_H, 0, (size_t)corr->n_lags * L.n_bins * 8), "zero H");
+    TRYHIP(hipMemset(p->d_self, 0, (size_t)corr->n_lags * 8), "zero self");
+
+    sdc::CountArgs ca{};
+    ca.pairs = p->d_pairs;
+    ca.streams = p->d_streams;
+    ca.n_streams = (int)L.streams.size();
+    ca.perm = p->d_perm;
+    ca.gtab = p->d_gtab;
+    ca.pos4 = p->d_pos4;
+    ca.e2 = p->d_e2;
+    ca.n_shells = L.n_shells;
+    ca.inv_w = L.n_shells ? (float)((double)L.n_shells / (double)bins->r_max) : 0.0f;
+    ca.kind = L.kind;
+    ca.L0 = L.L[0];
+    ca.L1 = L.L[1];
+    ca.L2 = L.L[2];
+    ca.W1 = L.W[1];
+    ca.W2 = L.W[2];
+    ca.win = L.win;
+    ca.counts = p->d_counts;
+    int e = sdc::launch_count(ca, nullptr);
+    if (e != 0) {
+        delete p;
+        return hip_err(e, "count kernel");
+    }
+    TRYHIP(hipDeviceSynchronize(), "count kernel");
+#undef TRY
+#undef TRYHIP
+    *out = p;
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_n_bins(const sdc_plan* plan, int64_t* n_bins) {
+    g_err.clear();
+    if (!plan || !n_bins) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    *n_bins = plan->lay.n_bins;
+    return SDC_OK;
+}
+
+sdc_status sdc_accumulate(sdc_plan* p, const float* spins_dev, int64_t n_frames, const int32_t* lags_host,
+                          int32_t n_lags_sel, void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    if (!spins_dev) return set_err(SDC_ERR_INVALID_ARG, "null spins");
+    const LagSel* sel = nullptr;
+    s = get_sel(p, lags_host, n_lags_sel, &sel);
+    if (s != SDC_OK) return s;
+    const int64_t need = (int64_t)(p->corr.n_origins - 1) * p->corr.origin_stride + sel->max_lag + 1;
+    if (n_frames < need) return set_err(SDC_ERR_INVALID_ARG, "n_frames too small for the origins and lags");
+    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    const Layout& L = p->lay;
+
+    sdc::PackArgs pa{};
+    pa.frames = spins_dev;
+    pa.n = L.n;
+    pa.n_frames = n_frames;
+    pa.n_pad = L.n_pad;
+    pa.perm = p->d_perm;
+    pa.n_origins = p->corr.n_origins;
+    pa.stride = p->corr.origin_stride;
+    pa.precision = p->corr.precision;
+    pa.O8 = p->O8;
+    pa.F8 = p->F8;
+    pa.n_phase = p->corr.origin_stride;
+    pa.frames_valid = std::min<int64_t>(n_frames, p->t_req);
+    pa.A = p->d_A;
+    pa.B = p->d_B;
+    const bool timing = (p->corr.flags & SDC_FLAG_TIMING) != 0;
+    hipStream_t hs = (hipStream_t)stream;
+    if (timing) SDC_HIP(hipEventRecord(p->ev[0], hs), "hipEventRecord");
+    int e = sdc::launch_pack(pa, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "pack kernel");
+    }
+
+    sdc::SelfArgs sa{};
+    sa.frames = spins_dev;
+    sa.n = L.n;
+    sa.n_frames = n_frames;
+    sa.n_origins = p->corr.n_origins;
+    sa.stride = p->corr.origin_stride;
+    sa.lags = sel->d_lags;
+    sa.n_sel = sel->n_sel;
+    sa.t_need = need;
+    sa.self = p->d_self;
+    sa.precision = p->corr.precision;
+    sa.H = p->d_H;
+    sa.n_bins = L.n_bins;
+    if (timing) SDC_HIP(hipEventRecord(p->ev[1], hs), "hipEventRecord");
+    e = sdc::launch_self(sa, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "self kernel");
+    }
+
+    sdc::FusedArgs fa;
+    s = fused_args(p, *sel, &fa);
+    if (s != SDC_OK) return s;
+    if (timing) SDC_HIP(hipEventRecord(p->ev[2], hs), "hipEventRecord");
+    e = sdc::launch_fused(fa, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "fused kernel");
+    }
+    if (timing) {
+        SDC_HIP(hipEventRecord(p->ev[3], hs), "hipEventRecord");
+        p->timed = true;
+    }
+    for (int t : sel->lags) p->n_org[t] += (double)p->corr.n_origins;
+    return SDC_OK;
+}
+
+sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, double* Csum_host,
+                        double* Cself_host, double* Ssum_host, double* Sself_host, void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    const Layout& L = p->lay;
+    const int nl = p->corr.n_lags;
+    hipStream_t hs = (hipStream_t)stream;
+    if (C_host && !p->d_C) {
+        s = dalloc(&p->d_C, (size_t)nl * L.n_bins, &p->owned);
+        if (s != SDC_OK) return s;
+    }
+    SDC_HIP(hipMemcpyAsync(p->d_norg, p->n_org.data(), nl * sizeof(double), hipMemcpyHostToDevice, hs), "upload n_org");
+    sdc::FinalArgs fa{};
+    fa.H = p->d_H;
+    fa.counts = p->d_counts;
+    fa.n_org = p->d_norg;
+    fa.self = p->d_self;
+    fa.n_bins = L.n_bins;
+    fa.n_sites = L.n;
+    fa.n_lags = nl;
+    fa.C = C_host ? p->d_C : nullptr;
+    fa.csum = p->d_fin;
+    fa.cself = p->d_fin + nl;
+    fa.ssum = p->d_fin + 2 * nl;
+    fa.sself = p->d_fin + 4 * nl;
+    int e = sdc::launch_finalize(fa, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "finalize kernels");
+    }
+    std::vector<double> fin(6 * (size_t)nl);
+    SDC_HIP(hipMemcpyAsync(fin.data(), p->d_fin, fin.size() * sizeof(double), hipMemcpyDeviceToHost, hs), "copy out");
+    if (C_host)
+        SDC_HIP(hipMemcpyAsync(C_host, p->d_C, (size_t)nl * L.n_bins * sizeof(double), hipMemcpyDeviceToHost, hs),
+                "copy C");
+    if (counts_host)
+        SDC_HIP(hipMemcpyAsync(counts_host, p->d_counts, (size_t)L.n_bins * 8, hipMemcpyDeviceToHost, hs), "copy counts");
+    hipError_t se = hipStreamSynchronize(hs);
+    if (se != hipSuccess) {
+        p->failed = true;
+        return hip_err((int)se, "finalize (or earlier queued work)");
+    }
+    if (Csum_host) std::memcpy(Csum_host, fin.data(), nl * sizeof(double));
+    if (Cself_host) std::memcpy(Cself_host, fin.data() + nl, nl * sizeof(double));
+    if (Ssum_host) std::memcpy(Ssum_host, fin.data() + 2 * nl, 2 * nl * sizeof(double));
+    if (Sself_host) std::memcpy(Sself_host, fin.data() + 4 * nl, 2 * nl * sizeof(double));
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double* self_host, void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t hs = (hipStream_t)stream;
+    const int nl = p->corr.n_lags;
+    if (H_host)
+        SDC_HIP(hipMemcpyAsync(H_host, p->d_H, (size_t)nl * p->lay.n_bins * 8, hipMemcpyDeviceToHost, hs), "copy H");
+    if (self_host) SDC_HIP(hipMemcpyAsync(self_host, p->d_self, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy self");
+    hipError_t se = hipStreamSynchronize(hs);
+    if (se != hipSuccess) {
+        p->failed = true;
+        return hip_err((int)se, "raw copy (or earlier queued work)");
+    }
+    if (n_org_host) std::memcpy(n_org_host, p->n_org.data(), nl * sizeof(double));
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_load_raw(sdc_plan* p, const double* H_host, const double* n_org_host, const double* self_host,
+                             void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    if (!H_host || !n_org_host || !self_host) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    const int nl = p->corr.n_lags;
+    for (int t = 0; t < nl; ++t)
+        if (!(n_org_host[t] >= 0.0)) return set_err(SDC_ERR_INVALID_ARG, "negative or NaN origin total");
+    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t hs = (hipStream_t)stream;
+    SDC_HIP(hipMemcpyAsync(p->d_H, H_host, (size_t)nl * p->lay.n_bins * 8, hipMemcpyHostToDevice, hs), "load H");
+    SDC_HIP(hipMemcpyAsync(p->d_self, self_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load self");
+    hipError_t se = hipStreamSynchronize(hs);
+    if (se != hipSuccess) {
+        p->failed = true;
+        return hip_err((int)se, "load raw");
+    }
+    p->n_org.assign(n_org_host, n_org_host + nl);
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_timings(sdc_plan* p, double* ms) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    if (!ms) return set_err(SDC_ERR_INVALID_ARG, "null output");
+    if (!(p->corr.flags & SDC_FLAG_TIMING) || !p->timed)
+        return set_err(SDC_ERR_STATE, "no timed accumulate (create the plan with SDC_FLAG_TIMING)");
+    SDC_HIP(hipEventSynchronize(p->ev[3]), "hipEventSynchronize");
+    for (int k = 0; k < 3; ++k) {
+        float t = 0.0f;
+        SDC_HIP(hipEventElapsedTime(&t, p->ev[k], p->ev[k + 1]), "hipEventElapsedTime");
+        ms[k] = t;
+    }
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_reset(sdc_plan* p, void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    int e = sdc::launch_zero(p->d_H, (int64_t)p->corr.n_lags * p->lay.n_bins * 8, stream);
+    if (e == 0) e = sdc::launch_zero(p->d_self, (int64_t)p->corr.n_lags * 8, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "reset");
+    }
+    std::fill(p->n_org.begin(), p->n_org.end(), 0.0);
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_destroy(sdc_plan* p) {
+    g_err.clear();
+    if (!p) return SDC_OK;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    delete p;
+    return SDC_OK;
+}
+
+}  // extern "C"

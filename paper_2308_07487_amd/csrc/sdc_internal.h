@@ -1,0 +1,230 @@
+// Internal declarations of the sdc library: tile layout, kernel arguments and
+// launch wrappers.  Not part of the public ABI (include/sdc.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sdc.h"
+
+namespace sdc {
+
+// Sites are grouped in tiles of 64.  Periodic lattices: a tile is a brick of
+// at most 4x4x4 cells of one sublattice, slot (ox*4 + oy)*4 + oz.  Radial:
+// 64 consecutive points in Morton order.  Unused slots are padding (zero
+// spins, no counts).
+constexpr int kTile = 64;
+// Lags handled together by one fused task: 16 consecutive lag indices u.
+constexpr int kLagGroup = 16;
+// Origins per K-step of the fused product (two blocks of 8).
+constexpr int kKStep = 16;
+
+// One tile pair of a stream: i-tile, j-tile and the window shift of this pair.
+struct KPair {
+    int32_t ti, tj, shift, pad;
+};
+
+// A stream is a run of tile pairs whose epilogue shares one LDS histogram.
+// Periodic: all pairs (I, I + db) for a fixed brick offset db and fixed
+// sublattices; the histogram is indexed by the window coordinate and maps to
+// global bins through base/parity.  Radial: all pairs (I, J) of one I; the
+// histogram is indexed by shell.
+struct KStream {
+    int32_t p0, p1;
+    int32_t base[3];
+    int32_t parity;
+    int32_t pad[2];
+};
+
+// Lag group: lags t = s*(u0 + m) + phase for m in [0, 16) with bit m of mask.
+struct KGroup {
+    int32_t phase, u0, mask, pad;
+};
+
+struct Layout {
+    int kind = 0;
+    int L[3] = {0, 0, 0};
+    int64_t n = 0;
+    int64_t n_bins = 0;
+    int64_t n_pad = 0;
+    int32_t n_tiles = 0;
+    int W[3] = {1, 1, 1};   // periodic window extents
+    int win = 0;            // histogram bins per lag (window size or n_shells)
+    int n_shells = 0;
+    std::vector<int32_t> perm;   // [n_pad] original site index, -1 = padding
+    std::vector<int32_t> gtab;   // [n_pad] window coordinate of the slot
+    std::vector<float> pos4;     // [n_pad][4] radial positions, packed order
+    std::vector<float> e2;       // [n_shells] radial squared edges
+    std::vector<KPair> pairs;
+    std::vector<KStream> streams;
+};
+
+// Records the thread-local error text returned by sdc_last_error(); returns s.
+sdc_status set_error(sdc_status s, const std::string& msg);
+
+// Builds the tile layout of a sample.  Returns SDC_OK or an error with text.
+sdc_status build_layout(const float* pos, int64_t n, const sdc_bin_spec* spec,
+                        Layout* out, std::string* err);
+
+// Global bin of window coordinate w of stream s (periodic kinds).
+int64_t window_bin(const Layout& lay, const KStream& s, int w);
+
+// Radial shell of a squared distance: the largest k with e2[k] <= d2.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline int shell_of(float d2, const float* e2, int n_shells, float inv_w) {
+    // first guess from the square root, then move to the exact rule
+    float r = __builtin_sqrtf(d2);
+    int k = (int)(r * inv_w);
+    if (k < 0) k = 0;
+    if (k > n_shells - 1) k = n_shells - 1;
+    while (k > 0 && e2[k] > d2) --k;
+    while (k + 1 < n_shells && e2[k + 1] <= d2) ++k;
+    return k;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// multiply-xor bijection with Weyl key increments.  c is updated in place.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// FP32 squared distance in the fixed order ((dx*dx + dy*dy) + dz*dz), no
+// contraction.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline float dist2_f32(float xi, float yi, float zi, float xj, float yj, float zj) {
+#pragma clang fp contract(off)
+    float dx = xj - xi;
+    float dy = yj - yi;
+    float dz = zj - zi;
+    float a = dx * dx;
+    float b = dy * dy;
+    float c = dz * dz;
+    return (a + b) + c;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launch wrappers (sdc_kernels.hip).  All return hipError_t as int.
+// ---------------------------------------------------------------------------
+
+struct PackArgs {
+    const float* frames;  // [n_frames][n][3]
+    int64_t n, n_frames, n_pad;
+    const int32_t* perm;  // [n_pad]
+    int n_origins, stride, precision;
+    int O8;               // origin blocks of 8 in the A pack (per component)
+    int F8;               // frame blocks of 8 in each B phase pack
+    int n_phase;          // = stride
+    int64_t frames_valid; // frames usable: min(n_frames, required)
+    void* A;              // [3][O8][n_pad] x 32 B
+    void* B;              // [n_phase][3][F8][n_pad] x 32 B
+};
+int launch_pack(const PackArgs& a, void* stream);
+
+struct FusedArgs {
+    const void* A;
+    const void* B;
+    int64_t n_pad;
+    int O8, F8, n_c;
+    int64_t phase_stride;          // elements of 32 B per B phase
+    const KPair* pairs;
+    const KStream* streams;
+    int n_streams;
+    const KGroup* groups;
+    int n_groups;
+    const int32_t* gtab;
+    const float* pos4;
+    const float* e2;
+    int n_shells;
+    float inv_w;
+    int kind, L0, L1, L2, W1, W2, win;
+    double* H;
+    int64_t n_bins;
+    int stride;
+    int precision;
+};
+int launch_fused(const FusedArgs& a, void* stream);
+
+struct CountArgs {
+    const KPair* pairs;
+    const KStream* streams;
+    int n_streams;
+    const int32_t* perm;
+    const int32_t* gtab;
+    const float* pos4;
+    const float* e2;
+    int n_shells;
+    float inv_w;
+    int kind, L0, L1, L2, W1, W2, win;
+    unsigned long long* counts;
+};
+int launch_count(const CountArgs& a, void* stream);
+
+struct SelfArgs {
+    const float* frames;
+    int64_t n, n_frames;
+    int n_origins, stride;
+    const int32_t* lags;  // device [n_sel]
+    int n_sel;
+    int64_t t_need;       // frames read: (n_origins - 1) * stride + max lag + 1
+    double* self;         // [n_lags] indexed by lag value
+    int precision;        // split precisions: add the diagonal lo*lo term to H
+    double* H;            // [n_lags][n_bins]; the i = j pairs all fall in bin 0
+    int64_t n_bins;
+};
+int launch_self(const SelfArgs& a, void* stream);
+
+struct FinalArgs {
+    const double* H;
+    const unsigned long long* counts;
+    const double* n_org;   // device [n_lags]
+    const double* self;    // device [n_lags]
+    int64_t n_bins, n_sites;
+    int n_lags;
+    double* C;             // [n_lags][n_bins] or null
+    double* csum;          // [n_lags]
+    double* cself;         // [n_lags]
+    double* ssum;          // [n_lags][2]
+    double* sself;         // [n_lags][2]
+};
+int launch_finalize(const FinalArgs& a, void* stream);
+
+int launch_zero(void* ptr, int64_t bytes, void* stream);
+
+struct TrajArgs {
+    int64_t n;
+    int z_max;                 // neighbours per site (ELL width)
+    const int32_t* nbr;        // [n][z_max], -1 = none
+    const float* jval;         // [n][z_max]
+    float dt;
+    int init, pad;
+    double sigma;
+    uint64_t seed;
+    const float* init_dev;
+    float* frames;             // [n_frames][n][3]
+    int64_t n_frames;
+    float* work;               // [5][n][3] fp32 scratch: S, T, acc, k
+};
+int launch_traj(const TrajArgs& a, void* stream);
+
+int fused_lds_bytes(int win);
+
+}  // namespace sdc

@@ -1,0 +1,788 @@
+// gfx950 kernels of the sdc library.
+//
+//  pack    : [T][N][3] fp32 trajectory -> component-major, site-permuted,
+//            K-contiguous blocks of 8 time samples (Sec. 3.2: the N x 3M
+//            rearrangement; Sec. 3.1: realization-major storage for
+//            coalescing), split into hi + lo halves for reduced precision.
+//  fused   : per lag the N x N x 3*n_origins product on MFMA with the bin key
+//            and the histogram fused into the epilogue (Sec. 3.3-3.4, Fig. 2,
+//            Eq. (6)); LDS histograms in FP64, merged into global FP64 bins.
+//  count   : exact integer pair counts per bin with the same tile walk.
+//  self    : the i = j term per lag in FP64.
+//  final   : normalisation, site sum and the windowed time DFT (Sec. 2.2).
+//  traj    : Landau-Lifshitz RK4 (Eq. (2), Sec. 3.1) with Philox4x32-10 starts.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "sdc_internal.h"
+
+namespace sdc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// 32-byte pack element: 8 time samples of one component of one site.
+// Split precisions: 8 hi halves then 8 lo halves.  FP32: 8 floats.
+struct alignas(16) Chunk {
+    uint4 x, y;
+};
+
+// ---------------------------------------------------------------------------
+// pack
+// ---------------------------------------------------------------------------
+
+__device__ inline uint32_t bf16_bits(float v) {
+    __bf16 b = (__bf16)v;  // round to nearest even
+    return (uint32_t)__builtin_bit_cast(uint16_t, b);
+}
+__device__ inline uint32_t f16_bits(float v) {
+    _Float16 b = (_Float16)v;
+    return (uint32_t)__builtin_bit_cast(uint16_t, b);
+}
+__device__ inline float bf16_val(uint32_t bits) {
+    return (float)__builtin_bit_cast(__bf16, (uint16_t)bits);
+}
+__device__ inline float f16_val(uint32_t bits) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
+}
+
+template <int PREC>
+__device__ inline Chunk make_chunk(const float v[8]) {
+    Chunk c;
+    if constexpr (PREC == SDC_PREC_FP32) {
+        c.x = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                         __float_as_uint(v[3]));
+        c.y = make_uint4(__float_as_uint(v[4]), __float_as_uint(v[5]), __float_as_uint(v[6]),
+                         __float_as_uint(v[7]));
+    } else {
+        uint32_t hi[8], lo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if constexpr (PREC == SDC_PREC_SPLIT_BF16) {
+                hi[e] = bf16_bits(v[e]);
+                lo[e] = bf16_bits(v[e] - bf16_val(hi[e]));  // v - hi is exact in fp32
+            } else {
+                hi[e] = f16_bits(v[e]);
+                lo[e] = f16_bits(v[e] - f16_val(hi[e]));
+            }
+        }
+        c.x = make_uint4(hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16,
+                         hi[6] | hi[7] << 16);
+        c.y = make_uint4(lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16,
+                         lo[6] | lo[7] << 16);
+    }
+    return c;
+}
+
+// One thread per (block of 8 samples, packed site); writes the three
+// components.  Rows 0..3*O8 of the work index the A pack (origins o*s),
+// the rest the B packs (phase copies: sample g of phase ph is frame s*g + ph).
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_pad) return;
+    const int row = blockIdx.y;  // 0..O8 + n_phase*F8 - 1
+    const int32_t orig = a.perm[p];
+    float v[3][8];
+    const bool isA = row < a.O8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int64_t f;
+        bool ok;
+        if (isA) {
+            const int o = row * 8 + e;
+            f = (int64_t)o * a.stride;
+            ok = o < a.n_origins;
+        } else {
+            const int r = row - a.O8;
+            const int ph = r / a.F8;
+            const int g = (r % a.F8) * 8 + e;
+            f = (int64_t)g * a.stride + ph;
+            ok = true;
+        }
+        ok = ok && orig >= 0 && f < a.frames_valid;
+        const float* src = a.frames + (f * a.n + (ok ? orig : 0)) * 3;
+        v[0][e] = ok ? src[0] : 0.0f;
+        v[1][e] = ok ? src[1] : 0.0f;
+        v[2][e] = ok ? src[2] : 0.0f;
+    }
+    Chunk* dst;
+    int64_t comp_stride;
+    if (isA) {
+        dst = (Chunk*)a.A + (int64_t)row * a.n_pad + p;
+        comp_stride = (int64_t)a.O8 * a.n_pad;
+    } else {
+        const int r = row - a.O8;
+        const int ph = r / a.F8;
+        dst = (Chunk*)a.B + ((int64_t)ph * 3 * a.F8 + (r % a.F8)) * a.n_pad + p;
+        comp_stride = (int64_t)a.F8 * a.n_pad;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c * comp_stride] = make_chunk<PREC>(v[c]);
+}
+
+int launch_pack(const PackArgs& a, void* stream) {
+    dim3 block(256);
+    dim3 grid((unsigned)((a.n_pad + 255) / 256), (unsigned)(a.O8 + a.n_phase * a.F8));
+    hipStream_t s = (hipStream_t)stream;
+    switch (a.precision) {
+        case SDC_PREC_FP32: hipLaunchKernelGGL(pack_kernel<SDC_PREC_FP32>, grid, block, 0, s, a); break;
+        case SDC_PREC_SPLIT_BF16: hipLaunchKernelGGL(pack_kernel<SDC_PREC_SPLIT_BF16>, grid, block, 0, s, a); break;
+        case SDC_PREC_SPLIT_FP16: hipLaunchKernelGGL(pack_kernel<SDC_PREC_SPLIT_FP16>, grid, block, 0, s, a); break;
+        default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fused product + binning epilogue
+// ---------------------------------------------------------------------------
+//
+// Work: task = (lag group, stream).  A workgroup of 4 waves takes one task
+// and walks the stream's tile pairs (64 i-sites x 64 j-sites).  Wave w owns
+// the 32x32 quadrant (w >> 1, w & 1) for all 16 lags of the group: 16 MFMA
+// accumulator tiles.  The K loop runs over the 3 components and over
+// K-steps of 16 origins; in a K-step, lane (i, h) holds origins
+// 16c + 8h + [0, 8) of its site and lane (j, h) holds the 24 samples
+// 16c + 8h + u0 + [0, 24) of its site, from which the operand of lag u0 + m
+// is the 8-sample slice starting at m (a register select for even m, a byte
+// align for odd m).  No operand goes through LDS; LDS holds the histogram.
+
+__device__ inline uint32_t align2(uint32_t hi, uint32_t lo) {
+    return __builtin_amdgcn_alignbyte(hi, lo, 2);
+}
+
+template <int M>
+__device__ inline uint4 slice8(const uint32_t (&w)[12]) {
+    constexpr int e = M / 2;
+    if constexpr ((M & 1) == 0) {
+        return make_uint4(w[e], w[e + 1], w[e + 2], w[e + 3]);
+    } else {
+        return make_uint4(align2(w[e + 1], w[e]), align2(w[e + 2], w[e + 1]),
+                          align2(w[e + 3], w[e + 2]), align2(w[e + 4], w[e + 3]));
+    }
+}
+
+template <int PREC>
+__device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
+    if constexpr (PREC == SDC_PREC_SPLIT_BF16) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    } else {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+}
+
+template <int PREC, int M>
+__device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[12],
+                                  const uint32_t (&wl)[12], f32x16 (&acc)[16]) {
+    const uint4 bh = slice8<M>(wh);
+    const uint4 bl = slice8<M>(wl);
+    acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
+    acc[M] = mfma16<PREC>(av.x, bl, acc[M]);
+    acc[M] = mfma16<PREC>(av.y, bh, acc[M]);
+}
+
+template <int PREC, int... Ms>
+__device__ inline void split_all(const Chunk& av, const uint32_t (&wh)[12], const uint32_t (&wl)[12],
+                                 f32x16 (&acc)[16], std::integer_sequence<int, Ms...>) {
+    (split_step<PREC, Ms>(av, wh, wl, acc), ...);
+}
+
+template <int Q, int M>
+__device__ inline void f32_step(const float (&a)[8], const float (&w)[24], f32x16 (&acc)[16]) {
+    acc[M] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[Q], w[Q + M], acc[M], 0, 0, 0);
+}
+template <int Q, int... Ms>
+__device__ inline void f32_q(const float (&a)[8], const float (&w)[24], f32x16 (&acc)[16],
+                             std::integer_sequence<int, Ms...>) {
+    (f32_step<Q, Ms>(a, w, acc), ...);
+}
+template <int... Qs>
+__device__ inline void f32_all(const float (&a)[8], const float (&w)[24], f32x16 (&acc)[16],
+                               std::integer_sequence<int, Qs...>) {
+    (f32_q<Qs>(a, w, acc, std::make_integer_sequence<int, 16>{}), ...);
+}
+
+__device__ inline int pmod_dev(int a, int m) {
+    int r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+// Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
+// 24-sample B window (three pack elements).
+struct Stage {
+    Chunk a, b0, b1, b2;
+};
+
+typedef uint32_t u32x12 __attribute__((ext_vector_type(12)));
+
+template <int PREC>
+__device__ inline void stage_mma(const Stage& s, f32x16 (&acc)[16]) {
+    if constexpr (PREC == SDC_PREC_FP32) {
+        float af[8], w[24];
+        const uint32_t ar[8] = {s.a.x.x, s.a.x.y, s.a.x.z, s.a.x.w, s.a.y.x, s.a.y.y, s.a.y.z, s.a.y.w};
+        const uint32_t wr[24] = {s.b0.x.x, s.b0.x.y, s.b0.x.z, s.b0.x.w, s.b0.y.x, s.b0.y.y, s.b0.y.z, s.b0.y.w,
+                                 s.b1.x.x, s.b1.x.y, s.b1.x.z, s.b1.x.w, s.b1.y.x, s.b1.y.y, s.b1.y.z, s.b1.y.w,
+                                 s.b2.x.x, s.b2.x.y, s.b2.x.z, s.b2.x.w, s.b2.y.x, s.b2.y.y, s.b2.y.z, s.b2.y.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) af[e] = __uint_as_float(ar[e]);
+#pragma unroll
+        for (int e = 0; e < 24; ++e) w[e] = __uint_as_float(wr[e]);
+        f32_all(af, w, acc, std::make_integer_sequence<int, 8>{});
+    } else {
+        const uint32_t wh[12] = {s.b0.x.x, s.b0.x.y, s.b0.x.z, s.b0.x.w, s.b1.x.x, s.b1.x.y,
+                                 s.b1.x.z, s.b1.x.w, s.b2.x.x, s.b2.x.y, s.b2.x.z, s.b2.x.w};
+        const uint32_t wl[12] = {s.b0.y.x, s.b0.y.y, s.b0.y.z, s.b0.y.w, s.b1.y.x, s.b1.y.y,
+                                 s.b1.y.z, s.b1.y.w, s.b2.y.x, s.b2.y.y, s.b2.y.z, s.b2.y.w};
+        split_all<PREC>(s.a, wh, wl, acc, std::make_integer_sequence<int, 16>{});
+    }
+}
+
+int fused_lds_bytes(int win) { return kLagGroup * win * (int)sizeof(double) + 1024 * (int)sizeof(float); }
+
+template <int PREC, int RADIAL>
+__global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
+    extern __shared__ double hist[];  // [16][win] FP64, then radial edges
+    float* e2s = (float*)(hist + kLagGroup * a.win);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1, h = lane >> 5, l32 = lane & 31;
+
+    // XCD-aware task order: consecutive tasks land on the same XCD.
+    const int n_tasks = a.n_groups * a.n_streams;
+    const int per = (n_tasks + 7) / 8;
+    const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (task >= n_tasks) return;
+    const KGroup grp = a.groups[task / a.n_streams];
+    const KStream st = a.streams[task % a.n_streams];
+
+    for (int x = tid; x < kLagGroup * a.win; x += 256) hist[x] = 0.0;
+    if constexpr (RADIAL) {
+        for (int x = tid; x < a.n_shells; x += 256) e2s[x] = a.e2[x];
+    }
+    __syncthreads();
+
+    const Chunk* Ab = (const Chunk*)a.A;
+    const Chunk* Bb = (const Chunk*)a.B + (int64_t)grp.phase * a.phase_stride;
+    const int nk = 3 * a.n_c;
+    const int ublk = grp.u0 / 8;
+
+    for (int p = st.p0; p < st.p1; ++p) {
+        const KPair pr = a.pairs[p];
+        const int64_t si = (int64_t)pr.ti * kTile + wi * 32 + l32;
+        const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
+        f32x16 acc[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[m][r] = 0.0f;
+
+        auto addrA = [&](int kk) {
+            const int alpha = kk / a.n_c, c = kk - alpha * a.n_c;
+            return Ab + ((int64_t)(alpha * a.O8 + 2 * c + h)) * a.n_pad + si;
+        };
+        auto addrB = [&](int kk) {
+            const int alpha = kk / a.n_c, c = kk - alpha * a.n_c;
+            return Bb + ((int64_t)(alpha * a.F8 + 2 * c + h + ublk)) * a.n_pad + sj;
+        };
+        // Three register buffers: while K-step kk is multiplied, the loads
+        // of kk + 1 and kk + 2 are in flight (indices clamp to the last step).
+        auto load = [&](Stage& b, int kk) {
+            kk = kk < nk ? kk : nk - 1;
+            b.a = *addrA(kk);
+            const Chunk* pb = addrB(kk);
+            b.b0 = pb[0];
+            b.b1 = pb[a.n_pad];
+            b.b2 = pb[2 * a.n_pad];
+        };
+        Stage s0, s1, s2;
+        load(s0, 0);
+        load(s1, 1);
+        // nk = 3 * n_c is a multiple of 3: the rotation needs no tail.
+        // The scheduling barriers keep each stage's loads ahead of its MFMAs.
+        for (int kk = 0; kk < nk; kk += 3) {
+            load(s2, kk + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mma<PREC>(s0, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            load(s0, kk + 3);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mma<PREC>(s1, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            load(s1, kk + 4);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mma<PREC>(s2, acc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // Epilogue: bin of each accumulator element, LDS FP64 add per lag.
+        // Accumulator register r of lane (l32, h) holds row 8(r/4) + 4h + r%4,
+        // column l32 of the wave's 32x32 quadrant.
+        const int64_t rowbase = (int64_t)pr.ti * kTile + wi * 32 + 4 * h;
+        int bin[16];
+        if constexpr (RADIAL) {
+            const float4 pj = *(const float4*)(a.pos4 + 4 * sj);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float4 pi = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
+                const float d2 = dist2_f32(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
+                bin[r] = shell_of(d2, e2s, a.n_shells, a.inv_w);
+            }
+        } else {
+            const int gj = a.gtab[sj] + pr.shift;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) bin[r] = gj - a.gtab[rowbase + 8 * (r / 4) + (r % 4)];
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            if ((grp.mask >> m) & 1) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) atomicAdd(&hist[m * a.win + bin[r]], (double)acc[m][r]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // Merge the stream's histogram into the global bins.
+    for (int x = tid; x < kLagGroup * a.win; x += 256) {
+        const int m = x / a.win;
+        const int w = x - m * a.win;
+        const double v = hist[x];
+        if (v != 0.0 && ((grp.mask >> m) & 1)) {
+            int64_t b;
+            if constexpr (RADIAL) {
+                b = w;
+            } else {
+                const int w0 = w / (a.W1 * a.W2);
+                const int w1 = (w / a.W2) % a.W1;
+                const int w2 = w % a.W2;
+                const int k0 = pmod_dev(st.base[0] + w0, a.L0);
+                const int k1 = pmod_dev(st.base[1] + w1, a.L1);
+                const int k2 = pmod_dev(st.base[2] + w2, a.L2);
+                b = ((int64_t)k0 * a.L1 + k1) * a.L2 + k2;
+                if (a.kind == SDC_BINS_PERIODIC_BCC) b = 2 * b + st.parity;
+            }
+            const int64_t t = (int64_t)a.stride * (grp.u0 + m) + grp.phase;
+            unsafeAtomicAdd(&a.H[t * a.n_bins + b], v);
+        }
+    }
+}
+
+template <int PREC>
+static int launch_fused_prec(const FusedArgs& a, hipStream_t s) {
+    const int lds = fused_lds_bytes(a.win);
+    const int n_tasks = a.n_groups * a.n_streams;
+    const int grid = 8 * ((n_tasks + 7) / 8);
+    hipError_t e;
+    if (a.kind == SDC_BINS_RADIAL) {
+        e = hipFuncSetAttribute((const void*)fused_kernel<PREC, 1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL((fused_kernel<PREC, 1>), dim3(grid), dim3(256), lds, s, a);
+    } else {
+        e = hipFuncSetAttribute((const void*)fused_kernel<PREC, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL((fused_kernel<PREC, 0>), dim3(grid), dim3(256), lds, s, a);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_fused(const FusedArgs& a, void* stream) {
+    if (a.n_groups * a.n_streams == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    switch (a.precision) {
+        case SDC_PREC_FP32: return launch_fused_prec<SDC_PREC_FP32>(a, s);
+        case SDC_PREC_SPLIT_BF16: return launch_fused_prec<SDC_PREC_SPLIT_BF16>(a, s);
+        case SDC_PREC_SPLIT_FP16: return launch_fused_prec<SDC_PREC_SPLIT_FP16>(a, s);
+        default: return (int)hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exact pair counts
+// ---------------------------------------------------------------------------
+
+template <int RADIAL>
+__global__ __launch_bounds__(256) void count_kernel(CountArgs a) {
+    extern __shared__ unsigned int hcount[];  // [win], then radial edges
+    float* e2s = (float*)(hcount + a.win);
+    const int tid = threadIdx.x;
+    const KStream st = a.streams[blockIdx.x];
+    for (int x = tid; x < a.win; x += 256) hcount[x] = 0u;
+    if constexpr (RADIAL) {
+        for (int x = tid; x < a.n_shells; x += 256) e2s[x] = a.e2[x];
+    }
+    __syncthreads();
+    for (int p = st.p0; p < st.p1; ++p) {
+        const KPair pr = a.pairs[p];
+        for (int e = tid; e < kTile * kTile; e += 256) {
+            const int64_t pi = (int64_t)pr.ti * kTile + (e >> 6);
+            const int64_t pj = (int64_t)pr.tj * kTile + (e & 63);
+            if (a.perm[pi] < 0 || a.perm[pj] < 0) continue;
+            int w;
+            if constexpr (RADIAL) {
+                const float4 ri = *(const float4*)(a.pos4 + 4 * pi);
+                const float4 rj = *(const float4*)(a.pos4 + 4 * pj);
+                w = shell_of(dist2_f32(ri.x, ri.y, ri.z, rj.x, rj.y, rj.z), e2s, a.n_shells, a.inv_w);
+            } else {
+                w = a.gtab[pj] - a.gtab[pi] + pr.shift;
+            }
+            atomicAdd(&hcount[w], 1u);
+        }
+    }
+    __syncthreads();
+    for (int w = tid; w < a.win; w += 256) {
+        const unsigned int v = hcount[w];
+        if (v == 0u) continue;
+        int64_t b;
+        if constexpr (RADIAL) {
+            b = w;
+        } else {
+            const int w0 = w / (a.W1 * a.W2);
+            const int w1 = (w / a.W2) % a.W1;
+            const int w2 = w % a.W2;
+            const int k0 = pmod_dev(st.base[0] + w0, a.L0);
+            const int k1 = pmod_dev(st.base[1] + w1, a.L1);
+            const int k2 = pmod_dev(st.base[2] + w2, a.L2);
+            b = ((int64_t)k0 * a.L1 + k1) * a.L2 + k2;
+            if (a.kind == SDC_BINS_PERIODIC_BCC) b = 2 * b + st.parity;
+        }
+        atomicAdd(&a.counts[b], (unsigned long long)v);
+    }
+}
+
+int launch_count(const CountArgs& a, void* stream) {
+    if (a.n_streams == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    const int lds = a.win * 4 + (a.kind == SDC_BINS_RADIAL ? a.n_shells * 4 : 0);
+    hipError_t e;
+    if (a.kind == SDC_BINS_RADIAL) {
+        e = hipFuncSetAttribute((const void*)count_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(count_kernel<1>, dim3(a.n_streams), dim3(256), lds, s, a);
+    } else {
+        e = hipFuncSetAttribute((const void*)count_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(count_kernel<0>, dim3(a.n_streams), dim3(256), lds, s, a);
+    }
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// self term: sum_o sum_i S_i(o s) . S_i(o s + t) in FP64
+// ---------------------------------------------------------------------------
+
+// Low part of the hi/lo split exactly as the pack kernel forms it.
+template <int PREC>
+__device__ inline double split_lo(float v) {
+    if constexpr (PREC == SDC_PREC_SPLIT_BF16) return (double)bf16_val(bf16_bits(v - bf16_val(bf16_bits(v))));
+    else if constexpr (PREC == SDC_PREC_SPLIT_FP16) return (double)f16_val(f16_bits(v - f16_val(f16_bits(v))));
+    else return 0.0;
+}
+
+// Block: up to 16 consecutive sites.  With USE_LDS their whole time series
+// sits in LDS; otherwise the samples are read from global memory.
+// Thread (site q = tid / 16, lane r = tid % 16) takes lags r, r + 16, ...
+// Besides the exact self sum it forms, for split precisions, the lo*lo
+// product that the three-product contraction leaves out, restricted to the
+// i = j pairs, and adds it to bin 0 (the bin of zero displacement for every
+// bin kind).  On the diagonal that term has a fixed sign, so dropping it
+// would bias C(0, 0); off the diagonal it is unbiased rounding noise.
+template <bool USE_LDS, int PREC>
+__global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_block) {
+    extern __shared__ float ser[];  // [t_need][sites_per_block][3]
+    __shared__ double part[1024];
+    __shared__ double part_lo[1024];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * sites_per_block;
+    const int nsb = (int)((a.n - i0) < sites_per_block ? (a.n - i0) : sites_per_block);
+    if constexpr (USE_LDS) {
+        for (int64_t x = tid; x < a.t_need * nsb * 3; x += 256) {
+            const int64_t f = x / (nsb * 3);
+            const int64_t rem = x - f * nsb * 3;
+            ser[f * sites_per_block * 3 + rem] = a.frames[(f * a.n + i0) * 3 + rem];
+        }
+    }
+    for (int x = tid; x < a.n_sel; x += 256) {
+        part[x] = 0.0;
+        part_lo[x] = 0.0;
+    }
+    __syncthreads();
+    const int q = tid / 16, r = tid % 16;
+    if (q < nsb) {
+        for (int l = r; l < a.n_sel; l += 16) {
+            const int t = a.lags[l];
+            double s = 0.0, sl = 0.0;
+            for (int o = 0; o < a.n_origins; ++o) {
+                const int64_t f0 = (int64_t)o * a.stride, f1 = f0 + t;
+                const float* x0;
+                const float* x1;
+                if constexpr (USE_LDS) {
+                    x0 = ser + (f0 * sites_per_block + q) * 3;
+                    x1 = ser + (f1 * sites_per_block + q) * 3;
+                } else {
+                    x0 = a.frames + (f0 * a.n + i0 + q) * 3;
+                    x1 = a.frames + (f1 * a.n + i0 + q) * 3;
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    s += (double)x0[c] * (double)x1[c];
+                    if constexpr (PREC != SDC_PREC_FP32) sl += split_lo<PREC>(x0[c]) * split_lo<PREC>(x1[c]);
+                }
+            }
+            atomicAdd(&part[l], s);
+            if constexpr (PREC != SDC_PREC_FP32) atomicAdd(&part_lo[l], sl);
+        }
+    }
+    __syncthreads();
+    for (int l = tid; l < a.n_sel; l += 256) {
+        unsafeAtomicAdd(&a.self[a.lags[l]], part[l]);
+        if constexpr (PREC != SDC_PREC_FP32) unsafeAtomicAdd(&a.H[(int64_t)a.lags[l] * a.n_bins], part_lo[l]);
+    }
+}
+
+template <bool USE_LDS>
+static void launch_self_kind(const SelfArgs& a, dim3 grid, int lds, hipStream_t s, int spb) {
+    switch (a.precision) {
+        case SDC_PREC_SPLIT_BF16:
+            hipLaunchKernelGGL((self_kernel<USE_LDS, SDC_PREC_SPLIT_BF16>), grid, dim3(256), lds, s, a, spb);
+            break;
+        case SDC_PREC_SPLIT_FP16:
+            hipLaunchKernelGGL((self_kernel<USE_LDS, SDC_PREC_SPLIT_FP16>), grid, dim3(256), lds, s, a, spb);
+            break;
+        default:
+            hipLaunchKernelGGL((self_kernel<USE_LDS, SDC_PREC_FP32>), grid, dim3(256), lds, s, a, spb);
+            break;
+    }
+}
+
+int launch_self(const SelfArgs& a, void* stream) {
+    if (a.n_sel == 0) return 0;
+    if (a.n_sel > 1024) return (int)hipErrorInvalidValue;
+    const int64_t budget = 96 * 1024;
+    const int64_t per_site = a.t_need * 3 * (int64_t)sizeof(float);
+    hipStream_t s = (hipStream_t)stream;
+    if (per_site <= budget) {
+        int spb = (int)(budget / per_site);
+        if (spb > 16) spb = 16;
+        const int lds = (int)(a.t_need * spb * 3 * sizeof(float));
+        const void* fns[3] = {(const void*)self_kernel<true, SDC_PREC_FP32>,
+                              (const void*)self_kernel<true, SDC_PREC_SPLIT_BF16>,
+                              (const void*)self_kernel<true, SDC_PREC_SPLIT_FP16>};
+        for (const void* f : fns) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e != hipSuccess) return (int)e;
+        }
+        launch_self_kind<true>(a, dim3((unsigned)((a.n + spb - 1) / spb)), lds, s, spb);
+    } else {
+        launch_self_kind<false>(a, dim3((unsigned)((a.n + 15) / 16)), 0, s, 16);
+    }
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// finalize: normalisation, site sums, windowed DFT (all FP64)
+// ---------------------------------------------------------------------------
+
+__global__ void normalize_kernel(FinalArgs a) {
+    const int64_t total = (int64_t)a.n_lags * a.n_bins;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = x / a.n_bins;
+        const int64_t b = x - t * a.n_bins;
+        const double den = a.n_org[t] * (double)a.counts[b];
+        a.C[x] = den > 0.0 ? a.H[x] / den : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void sums_kernel(FinalArgs a) {
+    __shared__ double red[256];
+    const int t = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < a.n_bins; b += 256) s += a.H[(int64_t)t * a.n_bins + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double d = (double)a.n_sites * a.n_org[t];
+        a.csum[t] = d > 0.0 ? red[0] / d : 0.0;
+        a.cself[t] = d > 0.0 ? a.self[t] / d : 0.0;
+    }
+}
+
+__global__ void dft_kernel(FinalArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = a.n_lags;
+    if (k >= m) return;
+    double re0 = 0, im0 = 0, re1 = 0, im1 = 0;
+    for (int t = 0; t < m; ++t) {
+        const double w = 0.5 * (1.0 + cospi((double)t / (double)m));
+        const int64_t kt = ((int64_t)k * t) % m;
+        double sn, cs;
+        sincospi(-2.0 * (double)kt / (double)m, &sn, &cs);
+        re0 += w * a.csum[t] * cs;
+        im0 += w * a.csum[t] * sn;
+        re1 += w * a.cself[t] * cs;
+        im1 += w * a.cself[t] * sn;
+    }
+    a.ssum[2 * k] = re0;
+    a.ssum[2 * k + 1] = im0;
+    a.sself[2 * k] = re1;
+    a.sself[2 * k + 1] = im1;
+}
+
+int launch_finalize(const FinalArgs& a, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (a.C) {
+        const int64_t total = (int64_t)a.n_lags * a.n_bins;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    }
+    hipLaunchKernelGGL(sums_kernel, dim3(a.n_lags), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(dft_kernel, dim3((a.n_lags + 63) / 64), dim3(64), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+__global__ void zero_kernel(uint32_t* p, int64_t words) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < words;
+         x += (int64_t)gridDim.x * blockDim.x)
+        p[x] = 0u;
+}
+
+int launch_zero(void* ptr, int64_t bytes, void* stream) {
+    if (bytes <= 0) return 0;
+    const int64_t words = bytes / 4;
+    int64_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t*)ptr, words);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// trajectory: Philox starts and LL RK4
+// ---------------------------------------------------------------------------
+
+__device__ inline float u24(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+__global__ void traj_init_kernel(TrajArgs a, float* S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    double x, y, z;
+    if (a.init == SDC_INIT_GIVEN) {
+        x = a.init_dev[3 * i];
+        y = a.init_dev[3 * i + 1];
+        z = a.init_dev[3 * i + 2];
+    } else {
+        uint32_t c[4] = {(uint32_t)i, 0u, (uint32_t)((uint64_t)i >> 32), 0u};
+        philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        const double u0 = (double)(c[0] >> 8) * (1.0 / 16777216.0);
+        const double u1 = (double)(c[1] >> 8) * (1.0 / 16777216.0);
+        if (a.init == SDC_INIT_UNIFORM) {
+            z = 2.0 * u0 - 1.0;
+            const double r = sqrt(fmax(0.0, 1.0 - z * z));
+            double sn, cs;
+            sincospi(2.0 * u1, &sn, &cs);
+            x = r * cs;
+            y = r * sn;
+        } else {
+            const double rr = sqrt(-2.0 * log(1.0 - u0));
+            double sn, cs;
+            sincospi(2.0 * u1, &sn, &cs);
+            const double v0 = a.sigma * rr * cs, v1 = a.sigma * rr * sn;
+            const double ang = sqrt(v0 * v0 + v1 * v1);
+            const double f = ang > 0.0 ? sin(ang) / ang : 1.0;
+            x = f * v0;
+            y = f * v1;
+            z = cos(ang);
+        }
+    }
+    S[3 * i] = (float)x;
+    S[3 * i + 1] = (float)y;
+    S[3 * i + 2] = (float)z;
+    a.frames[3 * i] = (float)x;
+    a.frames[3 * i + 1] = (float)y;
+    a.frames[3 * i + 2] = (float)z;
+}
+
+// One RK4 stage: k = (sum_j J_ij X_j) x X_i.
+//  stage 0: acc = k;      Tout = S + dt/2 k
+//  stage 1: acc += 2k;    Tout = S + dt/2 k
+//  stage 2: acc += 2k;    Tout = S + dt k
+//  stage 3: S += dt/6 (acc + k), frame written
+__global__ __launch_bounds__(256) void traj_stage_kernel(TrajArgs a, int stage, float* S,
+                                                         const float* X, float* Tout, float* acc,
+                                                         float* frame) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+    for (int e = 0; e < a.z_max; ++e) {
+        const int32_t j = a.nbr[i * a.z_max + e];
+        if (j < 0) continue;
+        const float J = a.jval[i * a.z_max + e];
+        h0 += J * X[3 * (int64_t)j];
+        h1 += J * X[3 * (int64_t)j + 1];
+        h2 += J * X[3 * (int64_t)j + 2];
+    }
+    const float x0 = X[3 * i], x1 = X[3 * i + 1], x2 = X[3 * i + 2];
+    const float k0 = h1 * x2 - h2 * x1;
+    const float k1 = h2 * x0 - h0 * x2;
+    const float k2 = h0 * x1 - h1 * x0;
+    const float s0 = S[3 * i], s1 = S[3 * i + 1], s2 = S[3 * i + 2];
+    if (stage == 0) {
+        acc[3 * i] = k0;
+        acc[3 * i + 1] = k1;
+        acc[3 * i + 2] = k2;
+    } else if (stage < 3) {
+        acc[3 * i] += 2.f * k0;
+        acc[3 * i + 1] += 2.f * k1;
+        acc[3 * i + 2] += 2.f * k2;
+    }
+    if (stage < 3) {
+        const float c = stage == 2 ? a.dt : 0.5f * a.dt;
+        Tout[3 * i] = s0 + c * k0;
+        Tout[3 * i + 1] = s1 + c * k1;
+        Tout[3 * i + 2] = s2 + c * k2;
+    } else {
+        const float c = a.dt / 6.0f;
+        const float n0 = s0 + c * (acc[3 * i] + k0);
+        const float n1 = s1 + c * (acc[3 * i + 1] + k1);
+        const float n2 = s2 + c * (acc[3 * i + 2] + k2);
+        S[3 * i] = n0;
+        S[3 * i + 1] = n1;
+        S[3 * i + 2] = n2;
+        frame[3 * i] = n0;
+        frame[3 * i + 1] = n1;
+        frame[3 * i + 2] = n2;
+    }
+}
+
+int launch_traj(const TrajArgs& a, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned grid = (unsigned)((a.n + 255) / 256);
+    float* S = a.work;
+    float* T1 = a.work + 3 * a.n;
+    float* T2 = a.work + 6 * a.n;
+    float* acc = a.work + 9 * a.n;
+    hipLaunchKernelGGL(traj_init_kernel, dim3(grid), dim3(256), 0, s, a, S);
+    for (int64_t f = 1; f < a.n_frames; ++f) {
+        float* frame = a.frames + f * a.n * 3;
+        hipLaunchKernelGGL(traj_stage_kernel, dim3(grid), dim3(256), 0, s, a, 0, S, (const float*)S, T1, acc, frame);
+        hipLaunchKernelGGL(traj_stage_kernel, dim3(grid), dim3(256), 0, s, a, 1, S, (const float*)T1, T2, acc, frame);
+        hipLaunchKernelGGL(traj_stage_kernel, dim3(grid), dim3(256), 0, s, a, 2, S, (const float*)T2, T1, acc, frame);
+        hipLaunchKernelGGL(traj_stage_kernel, dim3(grid), dim3(256), 0, s, a, 3, S, (const float*)T1, T2, acc, frame);
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace sdc

@@ -1,0 +1,247 @@
+// Trajectory generator entry point: bond tables on the host (nearest
+// neighbours of sc/bcc lattices, or J(r) pairs within a cutoff for open
+// samples), then the RK4 kernels of sdc_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sdc_internal.h"
+
+namespace {
+
+int64_t pmod(int64_t a, int64_t m) {
+    int64_t r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+// Random bond sign from Philox: counter (min(i,j), max(i,j), 1, 0).
+float bond_sign(uint64_t seed, int64_t i, int64_t j) {
+    const uint32_t a = (uint32_t)std::min(i, j), b = (uint32_t)std::max(i, j);
+    uint32_t c[4] = {a, b, 1u, 0u};
+    sdc::philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return (c[0] & 1u) ? -1.0f : 1.0f;
+}
+
+struct Bonds {
+    int z = 0;
+    std::vector<int32_t> nbr;
+    std::vector<float> jv;
+};
+
+sdc_status lattice_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, Bonds* b, std::string* err) {
+    const bool bcc = sp->kind == SDC_BINS_PERIODIC_BCC;
+    int64_t L[3];
+    for (int a = 0; a < 3; ++a) {
+        if (sp->cells[a] < 1) {
+            *err = "cells must be >= 1";
+            return SDC_ERR_INVALID_ARG;
+        }
+        L[a] = sp->cells[a];
+    }
+    const int64_t expect = (bcc ? 2 : 1) * L[0] * L[1] * L[2];
+    if (n != expect) {
+        *err = "n_sites must equal the lattice sites of the box";
+        return SDC_ERR_INVALID_ARG;
+    }
+    // doubled integer coordinates D = 2r (sc: even), periodic modulo 2L
+    std::vector<int64_t> D(3 * n);
+    std::unordered_map<int64_t, int64_t> index;
+    index.reserve((size_t)n * 2);
+    auto code = [&](const int64_t d[3]) {
+        return (pmod(d[0], 2 * L[0]) * (2 * L[1]) + pmod(d[1], 2 * L[1])) * (2 * L[2]) + pmod(d[2], 2 * L[2]);
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            const double p = 2.0 * pos[3 * i + a];
+            const double r = std::floor(p + 0.5);
+            if (!(std::fabs(p - r) <= 2e-3) || (!bcc && pmod((int64_t)r, 2) != 0)) {
+                *err = "position is not a lattice point";
+                return SDC_ERR_INVALID_ARG;
+            }
+            D[3 * i + a] = (int64_t)r;
+        }
+        if (bcc && (pmod(D[3 * i], 2) != pmod(D[3 * i + 1], 2) || pmod(D[3 * i], 2) != pmod(D[3 * i + 2], 2))) {
+            *err = "position is not a bcc lattice point";
+            return SDC_ERR_INVALID_ARG;
+        }
+        if (!index.emplace(code(&D[3 * i]), i).second) {
+            *err = "duplicate lattice site";
+            return SDC_ERR_INVALID_ARG;
+        }
+    }
+    std::vector<std::array<int, 3>> deltas;
+    if (!bcc) {
+        deltas = {{2, 0, 0}, {-2, 0, 0}, {0, 2, 0}, {0, -2, 0}, {0, 0, 2}, {0, 0, -2}};
+    } else {
+        for (int sx = -1; sx <= 1; sx += 2)
+            for (int sy = -1; sy <= 1; sy += 2)
+                for (int sz = -1; sz <= 1; sz += 2) deltas.push_back({sx, sy, sz});
+    }
+    b->z = (int)deltas.size();
+    b->nbr.resize((size_t)n * b->z);
+    b->jv.resize((size_t)n * b->z);
+    for (int64_t i = 0; i < n; ++i)
+        for (int e = 0; e < b->z; ++e) {
+            const int64_t d[3] = {D[3 * i] + deltas[e][0], D[3 * i + 1] + deltas[e][1], D[3 * i + 2] + deltas[e][2]};
+            auto it = index.find(code(d));
+            if (it == index.end()) {
+                *err = "lattice neighbour missing";
+                return SDC_ERR_INVALID_ARG;
+            }
+            const int64_t j = it->second;
+            b->nbr[i * b->z + e] = (int32_t)j;
+            float J = (float)sp->J;
+            if (sp->coupling == SDC_COUPLING_NN_RANDOM_SIGN) J = (float)std::fabs(sp->J) * bond_sign(sp->seed, i, j);
+            b->jv[i * b->z + e] = J;
+        }
+    return SDC_OK;
+}
+
+sdc_status cutoff_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, Bonds* b, std::string* err) {
+    if (!(sp->r_cut > 0.0f) || !std::isfinite(sp->r_cut)) {
+        *err = "r_cut must be finite and > 0";
+        return SDC_ERR_INVALID_ARG;
+    }
+    const float rc = sp->r_cut;
+    const float rc2 = rc * rc;
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(pos[3 * i + a])) {
+                *err = "non-finite position";
+                return SDC_ERR_INVALID_ARG;
+            }
+            lo[a] = std::min(lo[a], pos[3 * i + a]);
+        }
+    // cell list with cell edge r_cut
+    std::unordered_map<int64_t, std::vector<int64_t>> cells;
+    auto cell_of = [&](int64_t i, int64_t c[3]) {
+        for (int a = 0; a < 3; ++a) c[a] = (int64_t)std::floor((pos[3 * i + a] - lo[a]) / rc);
+    };
+    auto key = [](int64_t x, int64_t y, int64_t z) { return (x * 1048573 + y) * 1048573 + z; };
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        cell_of(i, c);
+        cells[key(c[0], c[1], c[2])].push_back(i);
+    }
+    std::vector<std::vector<std::pair<int32_t, float>>> nb(n);
+    size_t zmax = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        cell_of(i, c);
+        for (int64_t dx = -1; dx <= 1; ++dx)
+            for (int64_t dy = -1; dy <= 1; ++dy)
+                for (int64_t dz = -1; dz <= 1; ++dz) {
+                    auto it = cells.find(key(c[0] + dx, c[1] + dy, c[2] + dz));
+                    if (it == cells.end()) continue;
+                    for (int64_t j : it->second) {
+                        if (j == i) continue;
+                        const float d2 = sdc::dist2_f32(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], pos[3 * j],
+                                                        pos[3 * j + 1], pos[3 * j + 2]);
+                        if (d2 <= rc2) nb[i].push_back({(int32_t)j, (float)(sp->J * std::exp(-std::sqrt((double)d2)))});
+                    }
+                }
+        zmax = std::max(zmax, nb[i].size());
+    }
+    if (zmax > 4096) {
+        *err = "too many neighbours within r_cut";
+        return SDC_ERR_UNSUPPORTED;
+    }
+    b->z = (int)std::max<size_t>(zmax, 1);
+    b->nbr.assign((size_t)n * b->z, -1);
+    b->jv.assign((size_t)n * b->z, 0.0f);
+    for (int64_t i = 0; i < n; ++i) {
+        std::sort(nb[i].begin(), nb[i].end());
+        for (size_t e = 0; e < nb[i].size(); ++e) {
+            b->nbr[i * b->z + e] = nb[i][e].first;
+            b->jv[i * b->z + e] = nb[i][e].second;
+        }
+    }
+    return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_sites, const sdc_traj_spec* spec,
+                                        float* frames_dev, int64_t n_frames, int device, void* stream) {
+    auto sdc_internal_set_error = [](sdc_status st, const std::string& msg) { return sdc::set_error(st, msg); };
+    if (!positions_host || !spec || !frames_dev) return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    if (n_sites < 1 || n_sites > ((int64_t)1 << 26))
+        return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "n_sites out of range");
+    if (n_frames < 1) return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "n_frames must be >= 1");
+    if (!(spec->dt > 0.0) || !std::isfinite(spec->dt) || !std::isfinite(spec->J))
+        return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "dt must be > 0 and J finite");
+    if (spec->init < SDC_INIT_UNIFORM || spec->init > SDC_INIT_GIVEN)
+        return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "unknown init");
+    if (spec->init == SDC_INIT_GIVEN && !spec->init_dev)
+        return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "init_dev is null");
+    if (spec->init == SDC_INIT_PERTURBED_Z && !(spec->sigma >= 0.0))
+        return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "sigma must be >= 0");
+    Bonds b;
+    std::string err;
+    sdc_status s;
+    try {
+        if ((spec->kind == SDC_BINS_PERIODIC_SC || spec->kind == SDC_BINS_PERIODIC_BCC) &&
+            (spec->coupling == SDC_COUPLING_NN_UNIFORM || spec->coupling == SDC_COUPLING_NN_RANDOM_SIGN))
+            s = lattice_bonds(positions_host, n_sites, spec, &b, &err);
+        else if (spec->kind == SDC_BINS_RADIAL && spec->coupling == SDC_COUPLING_EXP_CUTOFF)
+            s = cutoff_bonds(positions_host, n_sites, spec, &b, &err);
+        else
+            return sdc_internal_set_error(SDC_ERR_UNSUPPORTED, "unsupported kind/coupling combination");
+    } catch (const std::bad_alloc&) {
+        return sdc_internal_set_error(SDC_ERR_OOM, "host allocation failed");
+    }
+    if (s != SDC_OK) return sdc_internal_set_error(s, err.c_str());
+
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+        return sdc_internal_set_error(SDC_ERR_NO_DEVICE, "no HIP device");
+    if (device < 0 || device >= count) return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "device out of range");
+    if (hipSetDevice(device) != hipSuccess) return sdc_internal_set_error(SDC_ERR_HIP, "hipSetDevice");
+    int32_t* d_nbr = nullptr;
+    float* d_j = nullptr;
+    float* d_work = nullptr;
+    auto cleanup = [&]() {
+        if (d_nbr) (void)hipFree(d_nbr);
+        if (d_j) (void)hipFree(d_j);
+        if (d_work) (void)hipFree(d_work);
+    };
+    if (hipMalloc(&d_nbr, b.nbr.size() * 4) != hipSuccess || hipMalloc(&d_j, b.jv.size() * 4) != hipSuccess ||
+        hipMalloc(&d_work, (size_t)12 * n_sites * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return sdc_internal_set_error(SDC_ERR_OOM, "hipMalloc failed");
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_nbr, b.nbr.data(), b.nbr.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_j, b.jv.data(), b.jv.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) {
+        cleanup();
+        return sdc_internal_set_error(SDC_ERR_HIP, hipGetErrorString(e));
+    }
+    sdc::TrajArgs ta{};
+    ta.n = n_sites;
+    ta.z_max = b.z;
+    ta.nbr = d_nbr;
+    ta.jval = d_j;
+    ta.dt = (float)spec->dt;
+    ta.init = spec->init;
+    ta.sigma = spec->sigma;
+    ta.seed = spec->seed;
+    ta.init_dev = spec->init_dev;
+    ta.frames = frames_dev;
+    ta.n_frames = n_frames;
+    ta.work = d_work;
+    int le = sdc::launch_traj(ta, stream);
+    hipError_t se = hipStreamSynchronize(hs);
+    cleanup();
+    if (le != 0) return sdc_internal_set_error(SDC_ERR_HIP, hipGetErrorString((hipError_t)le));
+    if (se != hipSuccess) return sdc_internal_set_error(SDC_ERR_HIP, hipGetErrorString(se));
+    return sdc_internal_set_error(SDC_OK, "");
+}

@@ -1,0 +1,276 @@
+"""Python binding of the sdc C ABI (include/sdc.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; this module
+converts numpy arrays and torch device tensors to pointers, calls the entry
+points with the same names, and turns status codes into exceptions.  torch is
+used only for device memory and streams.  If the compiled library is missing
+the import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdc.so")
+
+OK, ERR_INVALID_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED, ERR_NO_DEVICE = range(7)
+PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16 = 0, 1, 2
+BINS_SC, BINS_BCC, BINS_RADIAL = 0, 1, 2
+COUPLING_NN_UNIFORM, COUPLING_NN_RANDOM_SIGN, COUPLING_EXP_CUTOFF = 0, 1, 2
+INIT_UNIFORM, INIT_PERTURBED_Z, INIT_GIVEN = 0, 1, 2
+
+PRECISIONS = {"fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16, "split_fp16": PREC_SPLIT_FP16}
+
+
+class SdcError(RuntimeError):
+    def __init__(self, status, what, detail):
+        super().__init__(f"{what}: {status_string(status)} ({detail})")
+        self.status = status
+
+
+class BinSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("cells", ctypes.c_int32 * 3),
+                ("n_shells", ctypes.c_int32), ("r_max", ctypes.c_float)]
+
+
+class CorrSpec(ctypes.Structure):
+    _fields_ = [("n_origins", ctypes.c_int32), ("n_lags", ctypes.c_int32),
+                ("origin_stride", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class TrajSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("cells", ctypes.c_int32 * 3),
+                ("coupling", ctypes.c_int32), ("r_cut", ctypes.c_float), ("J", ctypes.c_double),
+                ("dt", ctypes.c_double), ("init", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("init_dev", ctypes.c_void_p)]
+
+
+EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize", "sdc_plan_raw",
+           "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset", "sdc_plan_destroy",
+           "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate")
+FLAG_TIMING = 1
+
+_lib = None
+
+
+def lib():
+    """Load libsdc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2308_07487_amd.build` (no fallback path exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sdc_plan_create.argtypes = [P, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec),
+                                      ctypes.c_int, ctypes.POINTER(P)]
+        L.sdc_plan_n_bins.argtypes = [P, ctypes.POINTER(i64)]
+        L.sdc_accumulate.argtypes = [P, P, i64, P, i32, P]
+        L.sdc_finalize.argtypes = [P, P, P, P, P, P, P, P]
+        L.sdc_plan_raw.argtypes = [P, P, P, P, P]
+        L.sdc_plan_load_raw.argtypes = [P, P, P, P, P]
+        L.sdc_plan_timings.argtypes = [P, P]
+        L.sdc_plan_reset.argtypes = [P, P]
+        L.sdc_plan_destroy.argtypes = [P]
+        L.sdc_status_string.argtypes = [ctypes.c_int]
+        L.sdc_status_string.restype = ctypes.c_char_p
+        L.sdc_last_error.argtypes = []
+        L.sdc_last_error.restype = ctypes.c_char_p
+        L.sdc_layout_keys.argtypes = [P, i64, ctypes.POINTER(BinSpec), P]
+        L.sdc_traj_generate.argtypes = [P, i64, ctypes.POINTER(TrajSpec), P, i64, ctypes.c_int, P]
+        for name in ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize",
+                     "sdc_plan_raw", "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset",
+                     "sdc_plan_destroy",
+                     "sdc_layout_keys", "sdc_traj_generate"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    return lib().sdc_status_string(int(s)).decode()
+
+
+def last_error():
+    return lib().sdc_last_error().decode()
+
+
+def _check(status, what):
+    if status != OK:
+        raise SdcError(status, what, last_error())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if str(t.dtype) != dtype_name or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype_name} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def bin_spec(kind, cells=(0, 0, 0), n_shells=0, r_max=0.0):
+    b = BinSpec()
+    b.kind = int(kind)
+    for a in range(3):
+        b.cells[a] = int(cells[a])
+    b.n_shells = int(n_shells)
+    b.r_max = float(r_max)
+    return b
+
+
+def corr_spec(n_origins, n_lags, precision="split_bf16", origin_stride=1, flags=0):
+    c = CorrSpec()
+    c.n_origins = int(n_origins)
+    c.n_lags = int(n_lags)
+    c.origin_stride = int(origin_stride)
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.flags = int(flags)
+    return c
+
+
+def layout_keys(positions, kind, cells=(0, 0, 0), n_shells=0, r_max=0.0):
+    """Host check of the tile layout: bin of every ordered pair [n][n]."""
+    pos = np.ascontiguousarray(positions, dtype=np.float32)
+    n = pos.shape[0]
+    out = np.zeros((n, n), dtype=np.int64)
+    b = bin_spec(kind, cells, n_shells, r_max)
+    _check(lib().sdc_layout_keys(_np_ptr(pos), n, ctypes.byref(b), _np_ptr(out)), "sdc_layout_keys")
+    return out
+
+
+class Plan:
+    """One sample's plan: positions and bin spec fixed, accumulation state on the GPU."""
+
+    def __init__(self, positions, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0),
+                 n_shells=0, r_max=0.0, origin_stride=1, device=0, timing=False):
+        self._h = None
+        pos = np.ascontiguousarray(positions, dtype=np.float32)
+        self.n_sites = pos.shape[0]
+        self.n_origins = int(n_origins)
+        self.n_lags = int(n_lags)
+        self.origin_stride = int(origin_stride)
+        self.bins = bin_spec(kind, cells, n_shells, r_max)
+        self.corr = corr_spec(n_origins, n_lags, precision, origin_stride,
+                              flags=FLAG_TIMING if timing else 0)
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib().sdc_plan_create(_np_ptr(pos), self.n_sites, ctypes.byref(self.bins),
+                                     ctypes.byref(self.corr), self.device, ctypes.byref(h)),
+               "sdc_plan_create")
+        self._h = h
+        nb = ctypes.c_int64()
+        _check(lib().sdc_plan_n_bins(self._h, ctypes.byref(nb)), "sdc_plan_n_bins")
+        self.n_bins = int(nb.value)
+
+    def accumulate(self, spins, lags=None, stream=None):
+        """spins: contiguous float32 device tensor [T][N][3]."""
+        if tuple(spins.shape[1:]) != (self.n_sites, 3):
+            raise ValueError("spins must have shape [T][n_sites][3]")
+        ptr = _dev_ptr(spins, "torch.float32")
+        if lags is None:
+            lp, nl = None, 0
+        else:
+            la = np.ascontiguousarray(lags, dtype=np.int32)
+            lp, nl = _np_ptr(la), la.shape[0]
+        _check(lib().sdc_accumulate(self._h, ptr, spins.shape[0], lp, nl, _stream_ptr(stream)),
+               "sdc_accumulate")
+
+    def finalize(self, stream=None, want_C=True):
+        """Returns dict with C [n_lags][n_bins], counts, Csum, Cself, Ssum, Sself (complex)."""
+        nl, nb = self.n_lags, self.n_bins
+        C = np.zeros((nl, nb), dtype=np.float64) if want_C else None
+        counts = np.zeros(nb, dtype=np.uint64)
+        cs = np.zeros(nl)
+        cf = np.zeros(nl)
+        ss = np.zeros((nl, 2))
+        sf = np.zeros((nl, 2))
+        _check(lib().sdc_finalize(self._h, _np_ptr(C) if C is not None else None, _np_ptr(counts),
+                                  _np_ptr(cs), _np_ptr(cf), _np_ptr(ss), _np_ptr(sf),
+                                  _stream_ptr(stream)), "sdc_finalize")
+        return dict(C=C, counts=counts, Csum=cs, Cself=cf, Ssum=ss[:, 0] + 1j * ss[:, 1],
+                    Sself=sf[:, 0] + 1j * sf[:, 1])
+
+    def raw(self, stream=None):
+        """(H [n_lags][n_bins], n_org [n_lags], self [n_lags]) as accumulated (FP64)."""
+        H = np.zeros((self.n_lags, self.n_bins))
+        no = np.zeros(self.n_lags)
+        sf = np.zeros(self.n_lags)
+        _check(lib().sdc_plan_raw(self._h, _np_ptr(H), _np_ptr(no), _np_ptr(sf), _stream_ptr(stream)),
+               "sdc_plan_raw")
+        return H, no, sf
+
+    def load_raw(self, H, n_org, self_raw, stream=None):
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        n_org = np.ascontiguousarray(n_org, dtype=np.float64)
+        self_raw = np.ascontiguousarray(self_raw, dtype=np.float64)
+        _check(lib().sdc_plan_load_raw(self._h, _np_ptr(H), _np_ptr(n_org), _np_ptr(self_raw),
+                                       _stream_ptr(stream)), "sdc_plan_load_raw")
+
+    def timings(self):
+        """(pack_ms, self_ms, fused_ms) of the last accumulate (timing plans only)."""
+        ms = np.zeros(3)
+        _check(lib().sdc_plan_timings(self._h, _np_ptr(ms)), "sdc_plan_timings")
+        return tuple(float(x) for x in ms)
+
+    def reset(self, stream=None):
+        _check(lib().sdc_plan_reset(self._h, _stream_ptr(stream)), "sdc_plan_reset")
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().sdc_plan_destroy(self._h), "sdc_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def traj_generate(positions, kind, frames_out, cells=(0, 0, 0), J=1.0, dt=0.01, coupling=0,
+                  r_cut=0.0, init=INIT_UNIFORM, sigma=0.0, seed=0, init_state=None, device=0,
+                  stream=None):
+    """LL RK4 frames into frames_out (float32 device tensor [T][N][3])."""
+    pos = np.ascontiguousarray(positions, dtype=np.float32)
+    sp = TrajSpec()
+    sp.kind = int(kind)
+    for a in range(3):
+        sp.cells[a] = int(cells[a])
+    sp.coupling = int(coupling)
+    sp.r_cut = float(r_cut)
+    sp.J = float(J)
+    sp.dt = float(dt)
+    sp.init = int(init)
+    sp.sigma = float(sigma)
+    sp.seed = int(seed)
+    sp.init_dev = _dev_ptr(init_state, "torch.float32").value if init_state is not None else None
+    if tuple(frames_out.shape[1:]) != (pos.shape[0], 3):
+        raise ValueError("frames_out must have shape [T][n_sites][3]")
+    _check(lib().sdc_traj_generate(_np_ptr(pos), pos.shape[0], ctypes.byref(sp),
+                                   _dev_ptr(frames_out, "torch.float32"), frames_out.shape[0],
+                                   int(device), _stream_ptr(stream)), "sdc_traj_generate")

@@ -1,0 +1,125 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+- the library loads and exports every function declared in include/sdc.h;
+- the tile layout maps every ordered pair to the same bin as the oracle's
+  key rule, bit for bit (periodic sc/bcc including ragged boxes, radial);
+- argument validation returns the documented status codes before any
+  device work.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2308_07487_amd import inputs, sdc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_match_header():
+    hdr = open(os.path.join(ROOT, "include", "sdc.h")).read()
+    declared = set(re.findall(r"^(?:sdc_status|const char\*)\s+(sdc_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    L = sdc.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(sdc.EXPORTS)
+
+
+@pytest.mark.parametrize("L", [(1, 1, 1), (2, 3, 4), (5, 6, 7), (8, 8, 8), (9, 4, 10), (11, 13, 3)])
+def test_layout_keys_sc_match_oracle(orc, L):
+    pos = inputs.sc_positions(L)
+    pos, _, _ = inputs.permute_sites(pos, np.zeros((1, pos.shape[0], 3), np.float32), seed=1)
+    n = pos.shape[0]
+    keys = sdc.layout_keys(pos, sdc.BINS_SC, cells=L)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ref = orc.pair_keys(pos, orc.SC, ii.ravel(), jj.ravel(), cells=L).reshape(n, n)
+    np.testing.assert_array_equal(keys, ref)
+
+
+@pytest.mark.parametrize("L", [(1, 1, 1), (2, 2, 3), (3, 5, 4), (6, 6, 6)])
+def test_layout_keys_bcc_match_oracle(orc, L):
+    pos = inputs.bcc_positions(L)
+    pos, _, _ = inputs.permute_sites(pos, np.zeros((1, pos.shape[0], 3), np.float32), seed=2)
+    n = pos.shape[0]
+    keys = sdc.layout_keys(pos, sdc.BINS_BCC, cells=L)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ref = orc.pair_keys(pos, orc.BCC, ii.ravel(), jj.ravel(), cells=L).reshape(n, n)
+    np.testing.assert_array_equal(keys, ref)
+
+
+@pytest.mark.parametrize("n,ns,rm", [(1, 1, 1.0), (100, 64, 10.0), (777, 1024, 50.0), (300, 7, 2.0)])
+def test_layout_keys_radial_match_oracle(orc, n, ns, rm):
+    pos = inputs.ball_positions(n, rm / 2, seed=n)
+    keys = sdc.layout_keys(pos, sdc.BINS_RADIAL, n_shells=ns, r_max=rm)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ref = orc.pair_keys(pos, orc.RADIAL, ii.ravel(), jj.ravel(), n_shells=ns, r_max=rm).reshape(n, n)
+    np.testing.assert_array_equal(keys, ref)
+
+
+def test_layout_keys_radial_edge_ties(orc):
+    """Points placed exactly on shell edges (squared distances equal to an edge)."""
+    w = 0.25
+    xs = np.array([0.0, 0.25, 0.5, 1.0, 1.75, 3.0], dtype=np.float32)
+    pos = np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], axis=1)
+    keys = sdc.layout_keys(pos, sdc.BINS_RADIAL, n_shells=12, r_max=12 * w)
+    n = pos.shape[0]
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ref = orc.pair_keys(pos, orc.RADIAL, ii.ravel(), jj.ravel(), n_shells=12, r_max=3.0).reshape(n, n)
+    np.testing.assert_array_equal(keys, ref)
+
+
+def _create(pos, bins, corr):
+    h = ctypes.c_void_p()
+    p = np.ascontiguousarray(pos, dtype=np.float32)
+    st = sdc.lib().sdc_plan_create(p.ctypes.data_as(ctypes.c_void_p), p.shape[0], ctypes.byref(bins),
+                                   ctypes.byref(corr), 0, ctypes.byref(h))
+    return st, h
+
+
+def test_validation_codes():
+    pos = inputs.sc_positions((4, 4, 4))
+    good_b = sdc.bin_spec(sdc.BINS_SC, (4, 4, 4))
+    good_c = sdc.corr_spec(8, 16)
+    cases = [
+        (sdc.corr_spec(0, 16), good_b),
+        (sdc.corr_spec(8, 0), good_b),
+        (sdc.corr_spec(8, 16, origin_stride=0), good_b),
+        (sdc.corr_spec(8, 16, precision=7), good_b),
+        (sdc.corr_spec(8, 16, flags=2), good_b),
+        (good_c, sdc.bin_spec(9, (4, 4, 4))),
+        (good_c, sdc.bin_spec(sdc.BINS_SC, (4, 4, 5))),       # wrong site count
+        (good_c, sdc.bin_spec(sdc.BINS_RADIAL, n_shells=0, r_max=1.0)),
+        (good_c, sdc.bin_spec(sdc.BINS_RADIAL, n_shells=8, r_max=0.0)),
+    ]
+    for corr, bins in cases:
+        st, h = _create(pos, bins, corr)
+        assert st == sdc.ERR_INVALID_ARG, (st, sdc.last_error())
+        assert not h.value
+    st, _ = _create(pos + 0.25, good_b, good_c)
+    assert st == sdc.ERR_INVALID_ARG and "lattice" in sdc.last_error()
+    st, _ = _create(pos, sdc.bin_spec(sdc.BINS_RADIAL, n_shells=5000, r_max=1.0), good_c)
+    assert st == sdc.ERR_UNSUPPORTED
+    # null pointers
+    h = ctypes.c_void_p()
+    assert sdc.lib().sdc_plan_create(None, 64, ctypes.byref(good_b), ctypes.byref(good_c), 0,
+                                     ctypes.byref(h)) == sdc.ERR_INVALID_ARG
+    assert sdc.lib().sdc_accumulate(None, None, 0, None, 0, None) == sdc.ERR_INVALID_ARG
+    assert sdc.lib().sdc_finalize(None, None, None, None, None, None, None, None) == sdc.ERR_INVALID_ARG
+    assert sdc.lib().sdc_plan_destroy(None) == sdc.OK
+    nb = ctypes.c_int64()
+    assert sdc.lib().sdc_plan_n_bins(None, ctypes.byref(nb)) == sdc.ERR_INVALID_ARG
+    for s in range(7):
+        assert sdc.status_string(s)
+
+
+def test_no_device_reported_on_host():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = _create(inputs.sc_positions((4, 4, 4)), sdc.bin_spec(sdc.BINS_SC, (4, 4, 4)),
+                    sdc.corr_spec(8, 16))
+    assert st == sdc.ERR_NO_DEVICE
+    assert not h.value

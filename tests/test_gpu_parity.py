@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars (see the tolerance derivation in the design notes):
+- pair counts: bit-exact;
+- dyadic inputs: raw bins H bit-exact for every precision;
+- FP32 and split-FP16: normwise error <= 1e-6 on C(r,t);
+- split-BF16: normwise error <= 5e-5 (deterministic bound 3*2^-16 plus FP32
+  accumulation); on random unit spins the off-diagonal rounding is unbiased
+  noise, bounded by six standard deviations for the sparsest bin and by 1e-6
+  once bins hold enough pairs x origins (the diagonal lo*lo term is added
+  exactly).
+Normwise error e = max |C_gpu - C_ref| / max |C_ref| over all bins and lags.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_07487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6, "split_fp16": 1e-6, "split_bf16": 5e-5}
+TOL_RANDOM = {"fp32": 1e-6, "split_fp16": 1e-6, "split_bf16": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2308_07487_amd import sdc
+    return sdc
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _run_gpu(torch, S, pos, frames, kind, n_o, n_L, prec, lags=None, stride=1, **kw):
+    with S.Plan(pos, kind, n_o, n_L, prec, origin_stride=stride, **kw) as p:
+        d = torch.from_numpy(frames).cuda()
+        p.accumulate(d, lags=lags)
+        out = p.finalize()
+        H, no, sf = p.raw()
+        torch.cuda.synchronize()
+    return out, H, no, sf
+
+
+def _oracle(orc, pos, frames, kind, n_o, lags, stride=1, **kw):
+    H, c = orc.binned_corr(pos, frames, kind, n_o, lags, stride=stride, **kw)
+    sf = orc.self_corr(frames, n_o, lags, stride=stride)
+    return H, c, sf
+
+
+def _tol_random(prec, counts, n_o):
+    """Random unit spins: split-BF16 rounding is unbiased noise of RMS about
+    2^-17 per product, so a bin's C error shrinks like 2^-17 / sqrt(count n_o);
+    the bar is six such standard deviations for the sparsest bin, and never
+    looser than needed above 1e-6."""
+    if prec != "split_bf16":
+        return TOL_RANDOM[prec]
+    m = float(np.min(counts[counts > 0])) * n_o
+    return max(TOL_RANDOM[prec], 6 * 2.0 ** -17 / np.sqrt(m))
+
+
+def _normwise(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+SC_CASES = [
+    # (name, L, n_o, n_L, stride)
+    ("c1-geometry 8^3", (8, 8, 8), 32, 64, 1),
+    ("ragged 5x6x7, n_o=20, n_L=21", (5, 6, 7), 20, 21, 1),
+    ("stride 3", (4, 4, 8), 10, 20, 3),
+    ("tiny 2x2x2", (2, 2, 2), 3, 5, 1),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("case", SC_CASES, ids=[c[0] for c in SC_CASES])
+def test_sc_random(torch_dev, S, orc, case, prec):
+    name, L, n_o, n_L, s = case
+    _say(f"sc {name} {prec}")
+    pos = inputs.sc_positions(L)
+    pos, _, _ = inputs.permute_sites(pos, np.zeros((1, pos.shape[0], 3), np.float32), seed=3)
+    T = (n_o - 1) * s + n_L
+    fr = inputs.random_unit_frames(T, pos.shape[0], seed=11)
+    out, H, no, sf = _run_gpu(torch_dev, S, pos, fr, S.BINS_SC, n_o, n_L, prec, stride=s, cells=L)
+    lags = np.arange(n_L)
+    Hr, cr, sfr = _oracle(orc, pos, fr, orc.SC, n_o, lags, stride=s, cells=L)
+    np.testing.assert_array_equal(out["counts"], cr)
+    C, Cs, Cf, Ss, Sf = orc.finalize(Hr, cr, pos.shape[0], float(n_o), sfr)
+    e = _normwise(out["C"], C)
+    print(f"  normwise error {e:.3e}", flush=True)
+    assert e <= _tol_random(prec, cr, n_o)
+    np.testing.assert_allclose(no, n_o)
+    np.testing.assert_allclose(sf, sfr, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(out["Cself"], Cf, rtol=1e-12, atol=1e-12)
+    assert _normwise(out["Csum"], Cs) <= TOL[prec] * 4
+    assert np.max(np.abs(out["Ssum"] - Ss)) <= TOL[prec] * 4 * n_L
+    np.testing.assert_allclose(out["Sself"], Sf, rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+def test_dyadic_bit_exact(torch_dev, S, orc, prec):
+    """Components in (1/16)Z: every product and partial sum is exact, so the
+    raw bins must agree bit for bit whatever the summation order."""
+    for kind, pos, kw in [
+        (S.BINS_SC, inputs.sc_positions((6, 5, 4)), dict(cells=(6, 5, 4))),
+        (S.BINS_BCC, inputs.bcc_positions((3, 3, 2)), dict(cells=(3, 3, 2))),
+        (S.BINS_RADIAL, inputs.ball_positions(150, 3.0, 5), dict(n_shells=40, r_max=6.0)),
+    ]:
+        _say(f"dyadic kind={kind} {prec}")
+        n_o, n_L = 8, 18
+        fr = inputs.dyadic_frames(n_o + n_L - 1, pos.shape[0], seed=kind + 1)
+        out, H, _, _ = _run_gpu(torch_dev, S, pos, fr, kind, n_o, n_L, prec, **kw)
+        Hr, cr, _ = _oracle(orc, pos, fr, kind, n_o, np.arange(n_L), **kw)
+        np.testing.assert_array_equal(out["counts"], cr)
+        np.testing.assert_array_equal(H, Hr)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_bcc_and_radial_random(torch_dev, S, orc, prec):
+    for kind, pos, kw in [
+        (S.BINS_BCC, inputs.bcc_positions((4, 3, 5)), dict(cells=(4, 3, 5))),
+        (S.BINS_RADIAL, inputs.ball_positions(700, 5.0, 8), dict(n_shells=1024, r_max=10.0)),
+        (S.BINS_RADIAL, inputs.ball_positions(130, 2.0, 9), dict(n_shells=33, r_max=3.0)),
+    ]:
+        _say(f"random kind={kind} n={pos.shape[0]} {prec}")
+        n_o, n_L = 17, 19
+        fr = inputs.random_unit_frames(n_o + n_L - 1, pos.shape[0], seed=21)
+        out, H, _, _ = _run_gpu(torch_dev, S, pos, fr, kind, n_o, n_L, prec, **kw)
+        Hr, cr, sfr = _oracle(orc, pos, fr, kind, n_o, np.arange(n_L), **kw)
+        np.testing.assert_array_equal(out["counts"], cr)
+        C, *_ = orc.finalize(Hr, cr, pos.shape[0], float(n_o), sfr)
+        e = _normwise(out["C"], C)
+        print(f"  normwise error {e:.3e}", flush=True)
+        assert e <= _tol_random(prec, cr, n_o)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+def test_static_ferromagnet_z_exact(torch_dev, S, prec):
+    """Every spin along z in every frame: C = 1 exactly in every occupied bin."""
+    _say(f"static z ferromagnet {prec}")
+    L = (4, 4, 6)
+    pos = inputs.sc_positions(L)
+    fr = inputs.static_frames(40, pos.shape[0], (0, 0, 1))
+    out, H, _, _ = _run_gpu(torch_dev, S, pos, fr, S.BINS_SC, 20, 21, prec, cells=L)
+    np.testing.assert_array_equal(out["C"], 1.0)
+    np.testing.assert_array_equal(out["Cself"], 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+def test_planted_spiral(torch_dev, S, prec):
+    _say(f"planted spiral {prec}")
+    L = (8, 4, 6)
+    pos = inputs.sc_positions(L)
+    q = 2 * np.pi * np.array([1, 1, 2]) / np.array(L)
+    theta, omega, dt = np.pi / 2, 0.9, 0.1
+    n_o, n_L = 16, 24
+    fr = inputs.spiral_frames(pos, q, theta, omega, n_o + n_L - 1, dt)
+    out, *_ = _run_gpu(torch_dev, S, pos, fr, S.BINS_SC, n_o, n_L, prec, cells=L)
+    b = np.arange(pos.shape[0])
+    d = np.stack([b // (L[1] * L[2]), (b // L[2]) % L[1], b % L[2]], axis=1)
+    t = np.arange(n_L)[:, None]
+    ref = np.cos(d @ q - omega * t * dt)
+    tol = {"fp32": 2e-6, "split_fp16": 2e-6, "split_bf16": 5e-5}[prec]
+    assert np.max(np.abs(out["C"] - ref)) <= tol
+
+
+def test_lag_subset_and_accumulation(torch_dev, S, orc):
+    _say("lag subset, two accumulates, reset, raw round trip")
+    L = (4, 5, 4)
+    pos = inputs.sc_positions(L)
+    n_o, n_L = 9, 40
+    fr1 = inputs.random_unit_frames(n_o + n_L, pos.shape[0], seed=1)
+    fr2 = inputs.random_unit_frames(n_o + n_L, pos.shape[0], seed=2)
+    lags = np.array([0, 5, 17, 39])
+    with S.Plan(pos, S.BINS_SC, n_o, n_L, "fp32", cells=L) as p:
+        p.accumulate(torch_dev.from_numpy(fr1).cuda(), lags=lags)
+        p.accumulate(torch_dev.from_numpy(fr2).cuda(), lags=lags[:2])
+        H, no, sf = p.raw()
+        H1, c1 = orc.binned_corr(pos, fr1, orc.SC, n_o, lags, cells=L)
+        H2, _ = orc.binned_corr(pos, fr2, orc.SC, n_o, lags[:2], cells=L)
+        ref = np.zeros((n_L, pos.shape[0]))
+        ref[lags] += H1
+        ref[lags[:2]] += H2
+        assert _normwise(H, ref) < 1e-6
+        expect_no = np.zeros(n_L)
+        expect_no[lags] += n_o
+        expect_no[lags[:2]] += n_o
+        np.testing.assert_array_equal(no, expect_no)
+        out = p.finalize()
+        untouched = np.setdiff1d(np.arange(n_L), lags)
+        np.testing.assert_array_equal(out["C"][untouched], 0.0)
+        # raw round trip and reset
+        p.reset()
+        H0, no0, _ = p.raw()
+        assert not H0.any() and not no0.any()
+        p.load_raw(H, no, sf)
+        H3, no3, sf3 = p.raw()
+        np.testing.assert_array_equal(H3, H)
+        np.testing.assert_array_equal(no3, no)
+
+
+def test_nan_propagates(torch_dev, S):
+    _say("nan propagation")
+    L = (4, 4, 4)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(40, 64, seed=4)
+    fr[3, 10, 1] = np.nan
+    out, H, _, _ = _run_gpu(torch_dev, S, pos, fr, S.BINS_SC, 8, 16, "split_bf16", cells=L)
+    assert np.isnan(H).any()
+
+
+def test_invalid_calls(torch_dev, S):
+    _say("invalid calls")
+    L = (4, 4, 4)
+    pos = inputs.sc_positions(L)
+    with S.Plan(pos, S.BINS_SC, 8, 16, "fp32", cells=L) as p:
+        d = torch_dev.zeros((10, 64, 3), device="cuda")
+        with pytest.raises(S.SdcError) as ei:
+            p.accumulate(d)  # needs 8 - 1 + 16 frames
+        assert ei.value.status == S.ERR_INVALID_ARG
+        with pytest.raises(S.SdcError):
+            p.accumulate(torch_dev.zeros((40, 64, 3), device="cuda"), lags=[16])
+        with pytest.raises(S.SdcError):
+            p.accumulate(torch_dev.zeros((40, 64, 3), device="cuda"), lags=[3, 3])
+        # the plan stays usable after rejected calls
+        p.accumulate(torch_dev.zeros((40, 64, 3), device="cuda"))
+        p.finalize()

@@ -1,0 +1,158 @@
+"""GPU trajectory generator (Landau-Lifshitz RK4, Eq. (2)) against the oracle.
+
+Initial states come from the seeded input generator (GIVEN) or from the
+library's Philox4x32-10 draws, which the oracle implements independently
+from the published definition.  The GPU integrates in FP32; the oracle in
+FP64, so short runs agree to ~1e-6.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_07487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2308_07487_amd import sdc
+    return sdc
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _nn_csr(pos, L, kind, J, sign_seed=None, orc=None):
+    n = pos.shape[0]
+    if kind == "sc":
+        D = np.rint(2 * pos).astype(int)
+        deltas = [(2, 0, 0), (-2, 0, 0), (0, 2, 0), (0, -2, 0), (0, 0, 2), (0, 0, -2)]
+    else:
+        D = np.rint(2 * pos).astype(int)
+        deltas = [(sx, sy, sz) for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
+    mod = 2 * np.array(L)
+    index = {tuple(x % mod): i for i, x in enumerate(D)}
+    cols, vals = [], []
+    for i in range(n):
+        for d in deltas:
+            j = index[tuple((D[i] + np.array(d)) % mod)]
+            cols.append(j)
+            if sign_seed is None:
+                vals.append(J)
+            else:
+                w = orc.philox_block([min(i, j), max(i, j), 1, 0],
+                                     [sign_seed & 0xFFFFFFFF, sign_seed >> 32])
+                vals.append(abs(J) * (-1.0 if w[0] & 1 else 1.0))
+    z = len(deltas)
+    return np.arange(n + 1, dtype=np.int64) * z, np.array(cols, np.int32), np.array(vals)
+
+
+def _cutoff_csr(pos, J, rc):
+    n = pos.shape[0]
+    rows, cols, vals = [0], [], []
+    rc2 = np.float32(rc) * np.float32(rc)
+    for i in range(n):
+        d = (pos - pos[i]).astype(np.float32)
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]).astype(np.float32) + (d[:, 2] * d[:, 2]).astype(np.float32)
+        js = [j for j in np.nonzero(d2 <= rc2)[0] if j != i]
+        for j in js:
+            cols.append(j)
+            vals.append(J * np.exp(-np.sqrt(np.float64(d2[j]))))
+        rows.append(len(cols))
+    return np.array(rows, np.int64), np.array(cols, np.int32), np.array(vals)
+
+
+def test_philox_initial_states(torch_dev, S, orc):
+    L = (6, 5, 4)
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    for mode, sigma in [(S.INIT_UNIFORM, 0.0), (S.INIT_PERTURBED_Z, 0.3)]:
+        _say(f"philox init mode={mode}")
+        fr = torch_dev.zeros((1, n, 3), device="cuda")
+        S.traj_generate(pos, S.BINS_SC, fr, cells=L, J=1.0, dt=0.01, init=mode, sigma=sigma,
+                        seed=0x5DC00002)
+        ref = orc.init_state(0x5DC00002, n, mode=mode, sigma=sigma)
+        np.testing.assert_allclose(fr.cpu().numpy()[0], ref, atol=1e-6)
+
+
+@pytest.mark.parametrize("kind,J", [("sc", 1.0), ("bcc", -1.0)])
+def test_rk4_matches_oracle(torch_dev, S, orc, kind, J):
+    _say(f"rk4 {kind} J={J}")
+    L = (5, 4, 6)
+    pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=17)[0]
+    nf = 30
+    fr = torch_dev.zeros((nf, n, 3), device="cuda")
+    S.traj_generate(pos, S.BINS_SC if kind == "sc" else S.BINS_BCC, fr, cells=L, J=J, dt=0.01,
+                    init=S.INIT_GIVEN, init_state=torch_dev.from_numpy(init).cuda())
+    row, col, Jv = _nn_csr(pos, L, kind, J)
+    ref = orc.ll_rk4(row, col, Jv, init, 0.01, nf)
+    np.testing.assert_allclose(fr.cpu().numpy(), ref, atol=5e-6)
+
+
+def test_rk4_random_sign_bonds(torch_dev, S, orc):
+    _say("rk4 random-sign bonds")
+    L = (4, 4, 4)
+    pos = inputs.bcc_positions(L)
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=5)[0]
+    seed = 0x5DC00517
+    fr = torch_dev.zeros((20, n, 3), device="cuda")
+    S.traj_generate(pos, S.BINS_BCC, fr, cells=L, J=1.0, dt=0.01, coupling=S.COUPLING_NN_RANDOM_SIGN,
+                    seed=seed, init=S.INIT_GIVEN, init_state=torch_dev.from_numpy(init).cuda())
+    row, col, Jv = _nn_csr(pos, L, "bcc", 1.0, sign_seed=seed, orc=orc)
+    assert (Jv < 0).any() and (Jv > 0).any()
+    ref = orc.ll_rk4(row, col, Jv, init, 0.01, 20)
+    np.testing.assert_allclose(fr.cpu().numpy(), ref, atol=5e-6)
+
+
+def test_rk4_exp_cutoff(torch_dev, S, orc):
+    _say("rk4 exp(-r) cutoff couplings")
+    pos = inputs.ball_positions(300, 3.0, seed=3)
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=6)[0]
+    fr = torch_dev.zeros((15, n, 3), device="cuda")
+    S.traj_generate(pos, S.BINS_RADIAL, fr, J=1.0, dt=0.005, coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5,
+                    init=S.INIT_GIVEN, init_state=torch_dev.from_numpy(init).cuda())
+    row, col, Jv = _cutoff_csr(pos, 1.0, 1.5)
+    assert col.shape[0] > n  # a connected sample
+    ref = orc.ll_rk4(row, col, Jv, init, 0.005, 15)
+    np.testing.assert_allclose(fr.cpu().numpy(), ref, atol=5e-6)
+
+
+def test_rk4_spin_wave_exact(torch_dev, S):
+    """The planted spin wave is an exact solution (w = J cos th (gamma_q - z))."""
+    _say("rk4 spin wave")
+    L = (8, 8, 4)
+    pos = inputs.sc_positions(L)
+    J, theta, dt, nf = 1.0, 0.7, 0.01, 201
+    q = 2 * np.pi * np.array([1, 2, 1]) / np.array(L)
+    gamma = 2 * np.cos(q).sum()
+    omega = J * np.cos(theta) * (gamma - 6)
+    exact = inputs.spiral_frames(pos, q, theta, omega, nf, dt)
+    fr = torch_dev.zeros((nf, pos.shape[0], 3), device="cuda")
+    S.traj_generate(pos, S.BINS_SC, fr, cells=L, J=J, dt=dt, init=S.INIT_GIVEN,
+                    init_state=torch_dev.from_numpy(exact[0].copy()).cuda())
+    err = np.abs(fr.cpu().numpy() - exact).max()
+    print(f"  max error {err:.2e}", flush=True)
+    assert err < 2e-5
+
+
+def test_rk4_conserves_magnetisation(torch_dev, S):
+    _say("rk4 M conservation")
+    L = (8, 8, 8)
+    pos = inputs.sc_positions(L)
+    fr = torch_dev.zeros((200, pos.shape[0], 3), device="cuda")
+    S.traj_generate(pos, S.BINS_SC, fr, cells=L, J=-1.0, dt=0.01, init=S.INIT_UNIFORM, seed=9)
+    M = fr.double().sum(dim=1).cpu().numpy()
+    assert np.abs(M - M[0]).max() < 1e-3  # fp32 rounding over 512 sites x 200 steps
+    assert np.abs(fr[-1].cpu().numpy() - fr[0].cpu().numpy()).max() > 1e-2

@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-check", action="store_true")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy"],
+                    help="copy: one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
@@ -158,6 +160,15 @@ def main():
 
     from paper_2308_07487_amd import sdc
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.mode == "copy":
+        n = 1 << 28  # 2^28 floats = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     N = int(np.prod(wl["L"]))
     terms = float(N) * N * wl["n_L"]

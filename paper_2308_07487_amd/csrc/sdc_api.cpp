@@ -66,10 +66,10 @@ sdc_status dalloc(T** p, size_t count, std::vector<void*>* owned) {
 
 // Groups of lags for one lag selection: lag t = s*u + phase, grouped by
 // (phase, 16-aligned block of u), with a mask of the selected members.
-std::vector<KGroup> make_groups(const std::vector<int>& lags, int s) {
+std::vector<KGroup> make_groups(const std::vector<int>& lags, int s, int lg) {
     std::map<std::pair<int, int>, int> mask;
     for (int t : lags) {
-        const int ph = t % s, u = t / s, u0 = (u / sdc::kLagGroup) * sdc::kLagGroup;
+        const int ph = t % s, u = t / s, u0 = (u / lg) * lg;
         mask[{ph, u0}] |= 1 << (u - u0);
     }
     std::vector<KGroup> g;
@@ -155,7 +155,7 @@ sdc_status get_sel(sdc_plan* p, const int32_t* lags_host, int32_t n_sel, const L
     sel.lags = lags;
     sel.n_sel = (int)lags.size();
     sel.max_lag = lags.back();
-    std::vector<KGroup> g = make_groups(lags, p->corr.origin_stride);
+    std::vector<KGroup> g = make_groups(lags, p->corr.origin_stride, sdc::lag_group(p->corr.precision));
     sel.n_groups = (int)g.size();
     sdc_status s = dalloc(&sel.d_groups, g.size(), &p->owned);
     if (s != SDC_OK) return s;
@@ -336,13 +336,15 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     p->n_c = (corr->n_origins + sdc::kKStep - 1) / sdc::kKStep;
     p->O8 = 2 * p->n_c;
     const int u_max = (corr->n_lags - 1) / sstr;
-    const int u0_max = (u_max / sdc::kLagGroup) * sdc::kLagGroup;
-    p->F8 = 2 * p->n_c + u0_max / 8 + 2;
+    const int lg = sdc::lag_group(corr->precision);
+    const int u0_max = (u_max / lg) * lg;
+    // largest block read: 2(n_c - 1) + 1 (half) + u0_max / 8 + win_blocks - 1
+    p->F8 = 2 * p->n_c + u0_max / 8 + sdc::win_blocks(lg) - 1;
     p->t_req = (int64_t)(corr->n_origins - 1) * sstr + corr->n_lags;
     p->bytes_A = (size_t)3 * p->O8 * L.n_pad * 32;
     p->bytes_B = (size_t)sstr * 3 * p->F8 * L.n_pad * 32;
     p->n_org.assign(corr->n_lags, 0.0);
-    if (sdc::fused_lds_bytes(L.win) > 160 * 1024) {
+    if (sdc::fused_lds_bytes(L.win, corr->precision) > 160 * 1024) {
         delete p;
         return set_err(SDC_ERR_UNSUPPORTED, "histogram window does not fit in LDS");
     }

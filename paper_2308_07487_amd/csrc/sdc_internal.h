@@ -15,8 +15,14 @@ namespace sdc {
 // 64 consecutive points in Morton order.  Unused slots are padding (zero
 // spins, no counts).
 constexpr int kTile = 64;
-// Lags handled together by one fused task: 16 consecutive lag indices u.
-constexpr int kLagGroup = 16;
+// Lags handled together by one fused task (consecutive lag indices u).
+// Split precisions take 8: a wave then holds 128 accumulator registers, two
+// workgroups fit on a CU and one workgroup's epilogue overlaps the other's
+// MFMA work.  FP32 takes 16 (one workgroup per CU): its MFMA is 16x slower
+// per flop, so operand reuse across more lags matters more than overlap.
+constexpr int lag_group(int precision) { return precision == SDC_PREC_FP32 ? 16 : 8; }
+// Pack elements (8 samples each) in one lane's B window: LG - 1 + 8 samples.
+constexpr int win_blocks(int lg) { return (lg + 14) / 8; }
 // Origins per K-step of the fused product (two blocks of 8).
 constexpr int kKStep = 16;
 
@@ -225,6 +231,6 @@ struct TrajArgs {
 };
 int launch_traj(const TrajArgs& a, void* stream);
 
-int fused_lds_bytes(int win);
+int fused_lds_bytes(int win, int precision);
 
 }  // namespace sdc

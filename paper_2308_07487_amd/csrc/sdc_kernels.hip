@@ -143,21 +143,25 @@ int launch_pack(const PackArgs& a, void* stream) {
 //
 // Work: task = (lag group, stream).  A workgroup of 4 waves takes one task
 // and walks the stream's tile pairs (64 i-sites x 64 j-sites).  Wave w owns
-// the 32x32 quadrant (w >> 1, w & 1) for all 16 lags of the group: 16 MFMA
+// the 32x32 quadrant (w >> 1, w & 1) for all LG lags of the group: LG MFMA
 // accumulator tiles.  The K loop runs over the 3 components and over
 // K-steps of 16 origins; in a K-step, lane (i, h) holds origins
-// 16c + 8h + [0, 8) of its site and lane (j, h) holds the 24 samples
-// 16c + 8h + u0 + [0, 24) of its site, from which the operand of lag u0 + m
-// is the 8-sample slice starting at m (a register select for even m, a byte
-// align for odd m).  No operand goes through LDS; LDS holds the histogram.
+// 16c + 8h + [0, 8) of its site and lane (j, h) holds the 8*NB samples
+// 16c + 8h + u0 + [0, 8*NB) of its site, from which the operand of lag
+// u0 + m is the 8-sample slice starting at m (a register select for even m,
+// a byte align for odd m).  No operand goes through LDS; LDS holds the
+// histogram.  Two workgroups share a CU, so one workgroup's epilogue and
+// memory waits overlap the other's MFMA work.
 
 __device__ inline uint32_t align2(uint32_t hi, uint32_t lo) {
     return __builtin_amdgcn_alignbyte(hi, lo, 2);
 }
 
-template <int M>
-__device__ inline uint4 slice8(const uint32_t (&w)[12]) {
+// Operand of lag u0 + M: the 8 halves starting at window element M.
+template <int M, int NW>
+__device__ inline uint4 slice8(const uint32_t (&w)[NW]) {
     constexpr int e = M / 2;
+    static_assert(e + 4 + (M & 1) <= NW, "window too short");
     if constexpr ((M & 1) == 0) {
         return make_uint4(w[e], w[e + 1], w[e + 2], w[e + 3]);
     } else {
@@ -177,35 +181,37 @@ __device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
     }
 }
 
-template <int PREC, int M>
-__device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[12],
-                                  const uint32_t (&wl)[12], f32x16 (&acc)[16]) {
-    const uint4 bh = slice8<M>(wh);
-    const uint4 bl = slice8<M>(wl);
+// Three-product split for lag u0 + M: hi*hi + hi*lo + lo*hi.
+template <int PREC, int M, int NW, int LG>
+__device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[NW],
+                                  const uint32_t (&wl)[NW], f32x16 (&acc)[LG]) {
+    const uint4 bh = slice8<M, NW>(wh);
+    const uint4 bl = slice8<M, NW>(wl);
     acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
     acc[M] = mfma16<PREC>(av.x, bl, acc[M]);
     acc[M] = mfma16<PREC>(av.y, bh, acc[M]);
 }
 
-template <int PREC, int... Ms>
-__device__ inline void split_all(const Chunk& av, const uint32_t (&wh)[12], const uint32_t (&wl)[12],
-                                 f32x16 (&acc)[16], std::integer_sequence<int, Ms...>) {
-    (split_step<PREC, Ms>(av, wh, wl, acc), ...);
+template <int PREC, int NW, int LG, int... Ms>
+__device__ inline void split_all(const Chunk& av, const uint32_t (&wh)[NW], const uint32_t (&wl)[NW],
+                                 f32x16 (&acc)[LG], std::integer_sequence<int, Ms...>) {
+    (split_step<PREC, Ms, NW, LG>(av, wh, wl, acc), ...);
 }
 
-template <int Q, int M>
-__device__ inline void f32_step(const float (&a)[8], const float (&w)[24], f32x16 (&acc)[16]) {
+// FP32: MFMA q of the K-step takes origin 16c + 8h + q on both sides.
+template <int Q, int M, int NF, int LG>
+__device__ inline void f32_step(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LG]) {
     acc[M] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[Q], w[Q + M], acc[M], 0, 0, 0);
 }
-template <int Q, int... Ms>
-__device__ inline void f32_q(const float (&a)[8], const float (&w)[24], f32x16 (&acc)[16],
+template <int Q, int NF, int LG, int... Ms>
+__device__ inline void f32_q(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LG],
                              std::integer_sequence<int, Ms...>) {
-    (f32_step<Q, Ms>(a, w, acc), ...);
+    (f32_step<Q, Ms, NF, LG>(a, w, acc), ...);
 }
-template <int... Qs>
-__device__ inline void f32_all(const float (&a)[8], const float (&w)[24], f32x16 (&acc)[16],
+template <int NF, int LG, int... Qs>
+__device__ inline void f32_all(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LG],
                                std::integer_sequence<int, Qs...>) {
-    (f32_q<Qs>(a, w, acc, std::make_integer_sequence<int, 16>{}), ...);
+    (f32_q<Qs, NF, LG>(a, w, acc, std::make_integer_sequence<int, LG>{}), ...);
 }
 
 __device__ inline int pmod_dev(int a, int m) {
@@ -214,54 +220,73 @@ __device__ inline int pmod_dev(int a, int m) {
 }
 
 // Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
-// 24-sample B window (three pack elements).
+// B window of NB pack elements.
+template <int NB>
 struct Stage {
-    Chunk a, b0, b1, b2;
+    Chunk a;
+    Chunk b[NB];
 };
 
-typedef uint32_t u32x12 __attribute__((ext_vector_type(12)));
-
-template <int PREC>
-__device__ inline void stage_mma(const Stage& s, f32x16 (&acc)[16]) {
+template <int PREC, int NB, int LG>
+__device__ inline void stage_mma(const Stage<NB>& s, f32x16 (&acc)[LG]) {
+    constexpr int NW = 4 * NB;
     if constexpr (PREC == SDC_PREC_FP32) {
-        float af[8], w[24];
+        float af[8], w[8 * NB];
         const uint32_t ar[8] = {s.a.x.x, s.a.x.y, s.a.x.z, s.a.x.w, s.a.y.x, s.a.y.y, s.a.y.z, s.a.y.w};
-        const uint32_t wr[24] = {s.b0.x.x, s.b0.x.y, s.b0.x.z, s.b0.x.w, s.b0.y.x, s.b0.y.y, s.b0.y.z, s.b0.y.w,
-                                 s.b1.x.x, s.b1.x.y, s.b1.x.z, s.b1.x.w, s.b1.y.x, s.b1.y.y, s.b1.y.z, s.b1.y.w,
-                                 s.b2.x.x, s.b2.x.y, s.b2.x.z, s.b2.x.w, s.b2.y.x, s.b2.y.y, s.b2.y.z, s.b2.y.w};
 #pragma unroll
         for (int e = 0; e < 8; ++e) af[e] = __uint_as_float(ar[e]);
 #pragma unroll
-        for (int e = 0; e < 24; ++e) w[e] = __uint_as_float(wr[e]);
-        f32_all(af, w, acc, std::make_integer_sequence<int, 8>{});
+        for (int k = 0; k < NB; ++k) {
+            const uint32_t r[8] = {s.b[k].x.x, s.b[k].x.y, s.b[k].x.z, s.b[k].x.w,
+                                   s.b[k].y.x, s.b[k].y.y, s.b[k].y.z, s.b[k].y.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[8 * k + e] = __uint_as_float(r[e]);
+        }
+        f32_all<8 * NB, LG>(af, w, acc, std::make_integer_sequence<int, 8>{});
     } else {
-        const uint32_t wh[12] = {s.b0.x.x, s.b0.x.y, s.b0.x.z, s.b0.x.w, s.b1.x.x, s.b1.x.y,
-                                 s.b1.x.z, s.b1.x.w, s.b2.x.x, s.b2.x.y, s.b2.x.z, s.b2.x.w};
-        const uint32_t wl[12] = {s.b0.y.x, s.b0.y.y, s.b0.y.z, s.b0.y.w, s.b1.y.x, s.b1.y.y,
-                                 s.b1.y.z, s.b1.y.w, s.b2.y.x, s.b2.y.y, s.b2.y.z, s.b2.y.w};
-        split_all<PREC>(s.a, wh, wl, acc, std::make_integer_sequence<int, 16>{});
+        uint32_t wh[NW], wl[NW];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            wh[4 * k] = s.b[k].x.x;
+            wh[4 * k + 1] = s.b[k].x.y;
+            wh[4 * k + 2] = s.b[k].x.z;
+            wh[4 * k + 3] = s.b[k].x.w;
+            wl[4 * k] = s.b[k].y.x;
+            wl[4 * k + 1] = s.b[k].y.y;
+            wl[4 * k + 2] = s.b[k].y.z;
+            wl[4 * k + 3] = s.b[k].y.w;
+        }
+        split_all<PREC, NW, LG>(s.a, wh, wl, acc, std::make_integer_sequence<int, LG>{});
     }
 }
 
-int fused_lds_bytes(int win) { return kLagGroup * win * (int)sizeof(double) + 1024 * (int)sizeof(float); }
+int fused_lds_bytes(int win, int precision) {
+    return lag_group(precision) * win * (int)sizeof(double) + 1024 * (int)sizeof(float);
+}
 
 template <int PREC, int RADIAL>
-__global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
-    extern __shared__ double hist[];  // [16][win] FP64, then radial edges
-    float* e2s = (float*)(hist + kLagGroup * a.win);
+__global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_kernel(FusedArgs a) {
+    constexpr int LG = lag_group(PREC);
+    constexpr int NB = win_blocks(LG);
+    extern __shared__ double hist[];  // [LG][win] FP64, then radial edges
+    float* e2s = (float*)(hist + LG * a.win);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1, h = lane >> 5, l32 = lane & 31;
 
-    // XCD-aware task order: consecutive tasks land on the same XCD.
+    // XCD-aware task order: consecutive tasks land on the same XCD (work-
+    // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
+    // the lag groups of one stream.  The workgroups running together on an
+    // XCD then walk the same tile pairs in step: they share the i-tile
+    // operand and overlapping time windows of the j-tile operand in L2.
     const int n_tasks = a.n_groups * a.n_streams;
     const int per = (n_tasks + 7) / 8;
     const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (task >= n_tasks) return;
-    const KGroup grp = a.groups[task / a.n_streams];
-    const KStream st = a.streams[task % a.n_streams];
+    const KGroup grp = a.groups[task % a.n_groups];
+    const KStream st = a.streams[task / a.n_groups];
 
-    for (int x = tid; x < kLagGroup * a.win; x += 256) hist[x] = 0.0;
+    for (int x = tid; x < LG * a.win; x += 256) hist[x] = 0.0;
     if constexpr (RADIAL) {
         for (int x = tid; x < a.n_shells; x += 256) e2s[x] = a.e2[x];
     }
@@ -276,9 +301,9 @@ __global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
         const KPair pr = a.pairs[p];
         const int64_t si = (int64_t)pr.ti * kTile + wi * 32 + l32;
         const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
-        f32x16 acc[16];
+        f32x16 acc[LG];
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
+        for (int m = 0; m < LG; ++m)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[m][r] = 0.0f;
 
@@ -290,34 +315,53 @@ __global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
             const int alpha = kk / a.n_c, c = kk - alpha * a.n_c;
             return Bb + ((int64_t)(alpha * a.F8 + 2 * c + h + ublk)) * a.n_pad + sj;
         };
-        // Three register buffers: while K-step kk is multiplied, the loads
-        // of kk + 1 and kk + 2 are in flight (indices clamp to the last step).
-        auto load = [&](Stage& b, int kk) {
+        // Register buffers: while K-step kk is multiplied the loads of later
+        // steps are in flight (indices clamp to the last step).
+        auto load = [&](Stage<NB>& b, int kk) {
             kk = kk < nk ? kk : nk - 1;
             b.a = *addrA(kk);
             const Chunk* pb = addrB(kk);
-            b.b0 = pb[0];
-            b.b1 = pb[a.n_pad];
-            b.b2 = pb[2 * a.n_pad];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) b.b[q] = pb[q * a.n_pad];
         };
-        Stage s0, s1, s2;
-        load(s0, 0);
-        load(s1, 1);
-        // nk = 3 * n_c is a multiple of 3: the rotation needs no tail.
-        // The scheduling barriers keep each stage's loads ahead of its MFMAs.
-        for (int kk = 0; kk < nk; kk += 3) {
-            load(s2, kk + 2);
-            __builtin_amdgcn_sched_barrier(0);
-            stage_mma<PREC>(s0, acc);
-            __builtin_amdgcn_sched_barrier(0);
-            load(s0, kk + 3);
-            __builtin_amdgcn_sched_barrier(0);
-            stage_mma<PREC>(s1, acc);
-            __builtin_amdgcn_sched_barrier(0);
-            load(s1, kk + 4);
-            __builtin_amdgcn_sched_barrier(0);
-            stage_mma<PREC>(s2, acc);
-            __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PREC == SDC_PREC_FP32) {
+            // One wave per SIMD: three buffers keep two K-steps of loads in
+            // flight.  nk = 3 * n_c is a multiple of 3, so the rotation needs
+            // no tail; the scheduling barriers keep loads ahead of the MFMAs.
+            Stage<NB> s0, s1, s2;
+            load(s0, 0);
+            load(s1, 1);
+            for (int kk = 0; kk < nk; kk += 3) {
+                load(s2, kk + 2);
+                __builtin_amdgcn_sched_barrier(0);
+                stage_mma<PREC, NB, LG>(s0, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                load(s0, kk + 3);
+                __builtin_amdgcn_sched_barrier(0);
+                stage_mma<PREC, NB, LG>(s1, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                load(s1, kk + 4);
+                __builtin_amdgcn_sched_barrier(0);
+                stage_mma<PREC, NB, LG>(s2, acc);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            // Two waves per SIMD: two buffers; the other wave covers the rest
+            // of the load latency.
+            Stage<NB> s0, s1;
+            load(s0, 0);
+            for (int kk = 0; kk < nk; kk += 2) {
+                load(s1, kk + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                stage_mma<PREC, NB, LG>(s0, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                if (kk + 1 < nk) {
+                    load(s0, kk + 2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    stage_mma<PREC, NB, LG>(s1, acc);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
         }
 
         // Epilogue: bin of each accumulator element, LDS FP64 add per lag.
@@ -339,7 +383,7 @@ __global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
             for (int r = 0; r < 16; ++r) bin[r] = gj - a.gtab[rowbase + 8 * (r / 4) + (r % 4)];
         }
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
+        for (int m = 0; m < LG; ++m) {
             if ((grp.mask >> m) & 1) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) atomicAdd(&hist[m * a.win + bin[r]], (double)acc[m][r]);
@@ -349,7 +393,7 @@ __global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
     __syncthreads();
 
     // Merge the stream's histogram into the global bins.
-    for (int x = tid; x < kLagGroup * a.win; x += 256) {
+    for (int x = tid; x < LG * a.win; x += 256) {
         const int m = x / a.win;
         const int w = x - m * a.win;
         const double v = hist[x];
@@ -375,7 +419,7 @@ __global__ __launch_bounds__(256, 1) void fused_kernel(FusedArgs a) {
 
 template <int PREC>
 static int launch_fused_prec(const FusedArgs& a, hipStream_t s) {
-    const int lds = fused_lds_bytes(a.win);
+    const int lds = fused_lds_bytes(a.win, PREC);
     const int n_tasks = a.n_groups * a.n_streams;
     const int grid = 8 * ((n_tasks + 7) / 8);
     hipError_t e;

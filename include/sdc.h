@@ -134,7 +134,10 @@ sdc_status sdc_plan_n_bins(const sdc_plan* plan, int64_t* n_bins);
  *  lags_host  : host array of n_lags_sel distinct lags in [0, n_lags), or
  *               NULL for all lags (then n_lags_sel is ignored).
  *  stream     : hipStream_t; everything is queued on it, nothing waits.
- * Repeated calls add; the per-lag origin totals add too.  Graph-capturable.
+ * Repeated calls add; the per-lag origin totals add too (they are kept on
+ * the device, so replays of a captured call count their origins).  Graph-
+ * capturable once the lag selection has been used in an uncaptured call
+ * (its first use uploads the selection's tables).
  * Errors: INVALID_ARG, STATE (plan failed earlier), HIP.
  */
 sdc_status sdc_accumulate(sdc_plan* plan, const float* spins_dev, int64_t n_frames,
@@ -182,8 +185,51 @@ sdc_status sdc_plan_timings(sdc_plan* plan, double* ms);
 sdc_status sdc_plan_reset(sdc_plan* plan, void* stream);
 
 /* Free the plan and its device memory (waits for the device).  NULL is a
- * no-op.  The pointer is invalid afterwards. */
+ * no-op.  The pointer is invalid afterwards.  Errors: STATE if a batch still
+ * holds the plan (destroy the batch first). */
 sdc_status sdc_plan_destroy(sdc_plan* plan);
+
+typedef struct sdc_batch sdc_batch;
+
+/*
+ * Group plans of several samples (the paper averages over many independent
+ * realizations, Sec. 2.2 and Sec. 4) so that one accumulate runs all their
+ * fused work as a single persistent launch: workgroups take (plan, stream,
+ * lag group) tasks from per-XCD queues until all are done.
+ *  plans   : n_plans distinct plans on one device, same precision, all
+ *            periodic or all radial; each keeps its own bins, counts and
+ *            origin totals.  Every lag of every plan is accumulated.
+ *  out     : receives the batch; it refers to the plans, which must outlive
+ *            it (sdc_plan_destroy refuses a plan still in a batch).
+ * Uploads the per-plan kernel arguments once.  Errors: INVALID_ARG,
+ * UNSUPPORTED (more than 2^30 tasks), STATE (a plan failed earlier), OOM,
+ * HIP.
+ */
+sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, sdc_batch** out);
+
+/*
+ * Accumulate one trajectory per plan, all lags (as sdc_accumulate with
+ * lags_host = NULL on each plan), with one fused launch for the batch.
+ *  spins_dev : host array of n_plans device pointers, [n_frames[k]][N_k][3]
+ *              fp32 each, read-only until the stream reaches this work.
+ *  n_frames  : host array of n_plans frame counts, each large enough for
+ *              its plan's origins and lags.
+ * Queued on the stream, no allocation and no host synchronisation: graph-
+ * capturable (the queue counters are cleared by a kernel, not a memset).
+ * Calls on one batch must not overlap in time.
+ * Errors: INVALID_ARG, STATE, HIP (then every plan of the batch is marked
+ * failed).
+ */
+sdc_status sdc_batch_accumulate(sdc_batch* batch, const float* const* spins_dev,
+                                const int64_t* n_frames, void* stream);
+
+/* Total fused tasks of the batch and the persistent grid (workgroups).
+ * Either output may be NULL.  Errors: INVALID_ARG. */
+sdc_status sdc_batch_info(const sdc_batch* batch, int64_t* n_tasks, int32_t* grid);
+
+/* Free the batch (waits for the device); its plans stay valid.  NULL is a
+ * no-op. */
+sdc_status sdc_batch_destroy(sdc_batch* batch);
 
 /* Static description of a status code. */
 const char* sdc_status_string(sdc_status s);

@@ -51,6 +51,15 @@ sdc_status use_device(int device) {
     return SDC_OK;
 }
 
+// Makes `device` current only if it is not already (a no-op call sequence
+// inside a stream capture).
+hipError_t select_device(int device) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    return cur == device ? hipSuccess : hipSetDevice(device);
+}
+
 template <class T>
 sdc_status dalloc(T** p, size_t count, std::vector<void*>* owned) {
     *p = nullptr;
@@ -113,9 +122,9 @@ struct sdc_plan {
     void* d_A = nullptr;
     void* d_B = nullptr;
     size_t bytes_A = 0, bytes_B = 0;
-    std::vector<double> n_org;
     std::map<std::vector<int>, LagSel> sels;
     bool failed = false;
+    int batch_refs = 0;  // batches that hold this plan
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
 
@@ -227,7 +236,75 @@ sdc_status fused_args(const sdc_plan* p, const LagSel& sel, sdc::FusedArgs* a) {
     return SDC_OK;
 }
 
+sdc_status check_frames(const sdc_plan* p, const LagSel& sel, int64_t n_frames) {
+    const int64_t need = (int64_t)(p->corr.n_origins - 1) * p->corr.origin_stride + sel.max_lag + 1;
+    if (n_frames < need) return set_err(SDC_ERR_INVALID_ARG, "n_frames too small for the origins and lags");
+    return SDC_OK;
+}
+
+// Queue the pack and self kernels of one accumulate (the current device is
+// the plan's); with `timing`, events 0 and 1 bracket them.
+sdc_status queue_pack_self(sdc_plan* p, const LagSel& sel, const float* spins_dev, int64_t n_frames, void* stream,
+                           bool timing) {
+    const Layout& L = p->lay;
+    hipStream_t hs = (hipStream_t)stream;
+    sdc::PackArgs pa{};
+    pa.frames = spins_dev;
+    pa.n = L.n;
+    pa.n_frames = n_frames;
+    pa.n_pad = L.n_pad;
+    pa.perm = p->d_perm;
+    pa.n_origins = p->corr.n_origins;
+    pa.stride = p->corr.origin_stride;
+    pa.precision = p->corr.precision;
+    pa.O8 = p->O8;
+    pa.F8 = p->F8;
+    pa.n_phase = p->corr.origin_stride;
+    pa.frames_valid = std::min<int64_t>(n_frames, p->t_req);
+    pa.A = p->d_A;
+    pa.B = p->d_B;
+    if (timing) SDC_HIP(hipEventRecord(p->ev[0], hs), "hipEventRecord");
+    int e = sdc::launch_pack(pa, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "pack kernel");
+    }
+    sdc::SelfArgs sa{};
+    sa.frames = spins_dev;
+    sa.n = L.n;
+    sa.n_frames = n_frames;
+    sa.n_origins = p->corr.n_origins;
+    sa.stride = p->corr.origin_stride;
+    sa.lags = sel.d_lags;
+    sa.n_sel = sel.n_sel;
+    sa.t_need = (int64_t)(p->corr.n_origins - 1) * p->corr.origin_stride + sel.max_lag + 1;
+    sa.self = p->d_self;
+    sa.precision = p->corr.precision;
+    sa.H = p->d_H;
+    sa.n_bins = L.n_bins;
+    sa.norg = p->d_norg;
+    if (timing) SDC_HIP(hipEventRecord(p->ev[1], hs), "hipEventRecord");
+    e = sdc::launch_self(sa, stream);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "self kernel");
+    }
+    return SDC_OK;
+}
+
 }  // namespace
+
+struct sdc_batch {
+    int device = 0;
+    std::vector<sdc_plan*> plans;
+    std::vector<const LagSel*> sels;
+    std::vector<void*> owned;
+    sdc::BatchLaunch bl{};
+    ~sdc_batch() {
+        for (sdc_plan* p : plans) --p->batch_refs;
+        for (void* q : owned) (void)hipFree(q);
+    }
+};
 
 extern "C" {
 
@@ -343,8 +420,7 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     p->t_req = (int64_t)(corr->n_origins - 1) * sstr + corr->n_lags;
     p->bytes_A = (size_t)3 * p->O8 * L.n_pad * 32;
     p->bytes_B = (size_t)sstr * 3 * p->F8 * L.n_pad * 32;
-    p->n_org.assign(corr->n_lags, 0.0);
-    if (sdc::fused_lds_bytes(L.win, corr->precision) > 160 * 1024) {
+    if (sdc::fused_lds_bytes(L.win, corr->precision) > sdc::kMaxFusedLds) {
         delete p;
         return set_err(SDC_ERR_UNSUPPORTED, "histogram window does not fit in LDS");
     }
@@ -366,6 +442,13 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
         }                                               \
     } while (0)
 
+    {
+        const int e = sdc::prepare_kernels();
+        if (e != 0) {
+            delete p;
+            return hip_err(e, "kernel attributes");
+        }
+    }
     TRY(dalloc(&p->d_perm, L.n_pad, &p->owned));
     TRY(dalloc(&p->d_gtab, L.n_pad, &p->owned));
     TRY(dalloc(&p->d_pos4, L.pos4.size(), &p->owned));
@@ -394,6 +477,7 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     TRYHIP(hipMemset(p->d_counts, 0, (size_t)L.n_bins * 8), "zero counts");
     TRYHIP(hipMemset(p->d_H, 0, (size_t)corr->n_lags * L.n_bins * 8), "zero H");
     TRYHIP(hipMemset(p->d_self, 0, (size_t)corr->n_lags * 8), "zero self");
+    TRYHIP(hipMemset(p->d_norg, 0, (size_t)corr->n_lags * 8), "zero origin totals");
 
     sdc::CountArgs ca{};
     ca.pairs = p->d_pairs;
@@ -441,60 +525,18 @@ sdc_status sdc_accumulate(sdc_plan* p, const float* spins_dev, int64_t n_frames,
     const LagSel* sel = nullptr;
     s = get_sel(p, lags_host, n_lags_sel, &sel);
     if (s != SDC_OK) return s;
-    const int64_t need = (int64_t)(p->corr.n_origins - 1) * p->corr.origin_stride + sel->max_lag + 1;
-    if (n_frames < need) return set_err(SDC_ERR_INVALID_ARG, "n_frames too small for the origins and lags");
-    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
-    const Layout& L = p->lay;
-
-    sdc::PackArgs pa{};
-    pa.frames = spins_dev;
-    pa.n = L.n;
-    pa.n_frames = n_frames;
-    pa.n_pad = L.n_pad;
-    pa.perm = p->d_perm;
-    pa.n_origins = p->corr.n_origins;
-    pa.stride = p->corr.origin_stride;
-    pa.precision = p->corr.precision;
-    pa.O8 = p->O8;
-    pa.F8 = p->F8;
-    pa.n_phase = p->corr.origin_stride;
-    pa.frames_valid = std::min<int64_t>(n_frames, p->t_req);
-    pa.A = p->d_A;
-    pa.B = p->d_B;
-    const bool timing = (p->corr.flags & SDC_FLAG_TIMING) != 0;
-    hipStream_t hs = (hipStream_t)stream;
-    if (timing) SDC_HIP(hipEventRecord(p->ev[0], hs), "hipEventRecord");
-    int e = sdc::launch_pack(pa, stream);
-    if (e != 0) {
-        p->failed = true;
-        return hip_err(e, "pack kernel");
-    }
-
-    sdc::SelfArgs sa{};
-    sa.frames = spins_dev;
-    sa.n = L.n;
-    sa.n_frames = n_frames;
-    sa.n_origins = p->corr.n_origins;
-    sa.stride = p->corr.origin_stride;
-    sa.lags = sel->d_lags;
-    sa.n_sel = sel->n_sel;
-    sa.t_need = need;
-    sa.self = p->d_self;
-    sa.precision = p->corr.precision;
-    sa.H = p->d_H;
-    sa.n_bins = L.n_bins;
-    if (timing) SDC_HIP(hipEventRecord(p->ev[1], hs), "hipEventRecord");
-    e = sdc::launch_self(sa, stream);
-    if (e != 0) {
-        p->failed = true;
-        return hip_err(e, "self kernel");
-    }
-
+    s = check_frames(p, *sel, n_frames);
+    if (s != SDC_OK) return s;
     sdc::FusedArgs fa;
     s = fused_args(p, *sel, &fa);
     if (s != SDC_OK) return s;
+    SDC_HIP(select_device(p->device), "hipSetDevice");
+    const bool timing = (p->corr.flags & SDC_FLAG_TIMING) != 0;
+    hipStream_t hs = (hipStream_t)stream;
+    s = queue_pack_self(p, *sel, spins_dev, n_frames, stream, timing);
+    if (s != SDC_OK) return s;
     if (timing) SDC_HIP(hipEventRecord(p->ev[2], hs), "hipEventRecord");
-    e = sdc::launch_fused(fa, stream);
+    const int e = sdc::launch_fused(fa, stream);
     if (e != 0) {
         p->failed = true;
         return hip_err(e, "fused kernel");
@@ -503,7 +545,6 @@ sdc_status sdc_accumulate(sdc_plan* p, const float* spins_dev, int64_t n_frames,
         SDC_HIP(hipEventRecord(p->ev[3], hs), "hipEventRecord");
         p->timed = true;
     }
-    for (int t : sel->lags) p->n_org[t] += (double)p->corr.n_origins;
     return SDC_OK;
 }
 
@@ -512,7 +553,7 @@ sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, doub
     g_err.clear();
     sdc_status s = plan_usable(p);
     if (s != SDC_OK) return s;
-    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    SDC_HIP(select_device(p->device), "hipSetDevice");
     const Layout& L = p->lay;
     const int nl = p->corr.n_lags;
     hipStream_t hs = (hipStream_t)stream;
@@ -520,7 +561,6 @@ sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, doub
         s = dalloc(&p->d_C, (size_t)nl * L.n_bins, &p->owned);
         if (s != SDC_OK) return s;
     }
-    SDC_HIP(hipMemcpyAsync(p->d_norg, p->n_org.data(), nl * sizeof(double), hipMemcpyHostToDevice, hs), "upload n_org");
     sdc::FinalArgs fa{};
     fa.H = p->d_H;
     fa.counts = p->d_counts;
@@ -562,18 +602,19 @@ sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double*
     g_err.clear();
     sdc_status s = plan_usable(p);
     if (s != SDC_OK) return s;
-    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    SDC_HIP(select_device(p->device), "hipSetDevice");
     hipStream_t hs = (hipStream_t)stream;
     const int nl = p->corr.n_lags;
     if (H_host)
         SDC_HIP(hipMemcpyAsync(H_host, p->d_H, (size_t)nl * p->lay.n_bins * 8, hipMemcpyDeviceToHost, hs), "copy H");
     if (self_host) SDC_HIP(hipMemcpyAsync(self_host, p->d_self, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy self");
+    if (n_org_host)
+        SDC_HIP(hipMemcpyAsync(n_org_host, p->d_norg, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy origin totals");
     hipError_t se = hipStreamSynchronize(hs);
     if (se != hipSuccess) {
         p->failed = true;
         return hip_err((int)se, "raw copy (or earlier queued work)");
     }
-    if (n_org_host) std::memcpy(n_org_host, p->n_org.data(), nl * sizeof(double));
     return SDC_OK;
 }
 
@@ -586,16 +627,16 @@ sdc_status sdc_plan_load_raw(sdc_plan* p, const double* H_host, const double* n_
     const int nl = p->corr.n_lags;
     for (int t = 0; t < nl; ++t)
         if (!(n_org_host[t] >= 0.0)) return set_err(SDC_ERR_INVALID_ARG, "negative or NaN origin total");
-    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    SDC_HIP(select_device(p->device), "hipSetDevice");
     hipStream_t hs = (hipStream_t)stream;
     SDC_HIP(hipMemcpyAsync(p->d_H, H_host, (size_t)nl * p->lay.n_bins * 8, hipMemcpyHostToDevice, hs), "load H");
     SDC_HIP(hipMemcpyAsync(p->d_self, self_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load self");
+    SDC_HIP(hipMemcpyAsync(p->d_norg, n_org_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load origin totals");
     hipError_t se = hipStreamSynchronize(hs);
     if (se != hipSuccess) {
         p->failed = true;
         return hip_err((int)se, "load raw");
     }
-    p->n_org.assign(n_org_host, n_org_host + nl);
     return SDC_OK;
 }
 
@@ -619,23 +660,154 @@ sdc_status sdc_plan_reset(sdc_plan* p, void* stream) {
     g_err.clear();
     sdc_status s = plan_usable(p);
     if (s != SDC_OK) return s;
-    SDC_HIP(hipSetDevice(p->device), "hipSetDevice");
+    SDC_HIP(select_device(p->device), "hipSetDevice");
     int e = sdc::launch_zero(p->d_H, (int64_t)p->corr.n_lags * p->lay.n_bins * 8, stream);
     if (e == 0) e = sdc::launch_zero(p->d_self, (int64_t)p->corr.n_lags * 8, stream);
+    if (e == 0) e = sdc::launch_zero(p->d_norg, (int64_t)p->corr.n_lags * 8, stream);
     if (e != 0) {
         p->failed = true;
         return hip_err(e, "reset");
     }
-    std::fill(p->n_org.begin(), p->n_org.end(), 0.0);
     return SDC_OK;
 }
 
 sdc_status sdc_plan_destroy(sdc_plan* p) {
     g_err.clear();
     if (!p) return SDC_OK;
+    if (p->batch_refs > 0) return set_err(SDC_ERR_STATE, "plan is held by a batch; destroy the batch first");
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     delete p;
+    return SDC_OK;
+}
+
+sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, sdc_batch** out) {
+    g_err.clear();
+    if (!out) return set_err(SDC_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (!plans) return set_err(SDC_ERR_INVALID_ARG, "null plan list");
+    if (n_plans < 1 || n_plans > 4096) return set_err(SDC_ERR_INVALID_ARG, "n_plans must be in [1, 4096]");
+    for (int k = 0; k < n_plans; ++k) {
+        sdc_status s = plan_usable(plans[k]);
+        if (s != SDC_OK) return s;
+        for (int q = 0; q < k; ++q)
+            if (plans[q] == plans[k]) return set_err(SDC_ERR_INVALID_ARG, "a plan appears twice in the batch");
+        if (plans[k]->device != plans[0]->device) return set_err(SDC_ERR_INVALID_ARG, "plans on different devices");
+        if (plans[k]->corr.precision != plans[0]->corr.precision)
+            return set_err(SDC_ERR_INVALID_ARG, "plans of different precisions");
+        if ((plans[k]->lay.kind == SDC_BINS_RADIAL) != (plans[0]->lay.kind == SDC_BINS_RADIAL))
+            return set_err(SDC_ERR_INVALID_ARG, "radial and periodic plans in one batch");
+    }
+    const int device = plans[0]->device;
+    const int prec = plans[0]->corr.precision;
+    const int radial = plans[0]->lay.kind == SDC_BINS_RADIAL ? 1 : 0;
+    SDC_HIP(hipSetDevice(device), "hipSetDevice");
+    sdc_batch* b = nullptr;
+    try {
+        b = new sdc_batch();
+    } catch (const std::bad_alloc&) {
+        return set_err(SDC_ERR_OOM, "host allocation failed");
+    }
+    b->device = device;
+    std::vector<sdc::FusedArgs> args((size_t)n_plans);
+    std::vector<int64_t> start((size_t)n_plans + 1, 0);
+    int lds = 0;
+    for (int k = 0; k < n_plans; ++k) {
+        sdc_plan* p = plans[k];
+        const LagSel* sel = nullptr;
+        sdc_status s = get_sel(p, nullptr, 0, &sel);
+        if (s == SDC_OK) s = fused_args(p, *sel, &args[k]);
+        if (s != SDC_OK) {
+            delete b;
+            return s;
+        }
+        b->plans.push_back(p);
+        ++p->batch_refs;
+        b->sels.push_back(sel);
+        start[k + 1] = start[k] + (int64_t)args[k].n_groups * args[k].n_streams;
+        lds = std::max(lds, sdc::fused_lds_bytes(args[k].win, prec));
+    }
+    if (start[n_plans] > (int64_t)INT32_MAX / 2) {
+        delete b;
+        return set_err(SDC_ERR_UNSUPPORTED, "too many fused tasks in the batch");
+    }
+    sdc::FusedArgs* d_args = nullptr;
+    int64_t* d_start = nullptr;
+    unsigned* d_queue = nullptr;
+    sdc_status s = dalloc(&d_args, args.size(), &b->owned);
+    if (s == SDC_OK) s = dalloc(&d_start, start.size(), &b->owned);
+    if (s == SDC_OK) s = dalloc(&d_queue, 8, &b->owned);
+    if (s != SDC_OK) {
+        delete b;
+        return s;
+    }
+    hipError_t he = hipMemcpy(d_args, args.data(), args.size() * sizeof(sdc::FusedArgs), hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+        he = hipMemcpy(d_start, start.data(), start.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+        delete b;
+        return hip_err((int)he, "upload batch tables");
+    }
+    sdc::BatchLaunch& bl = b->bl;
+    bl.args = d_args;
+    bl.task_start = d_start;
+    bl.n_plans = n_plans;
+    bl.queue = d_queue;
+    bl.total = (int)start[n_plans];
+    bl.precision = prec;
+    bl.radial = radial;
+    bl.lds = lds;
+    const int e = sdc::batch_grid(prec, radial, lds, device, std::max(bl.total, 1), &bl.grid);
+    if (e != 0) {
+        delete b;
+        return hip_err(e, "batch occupancy");
+    }
+    *out = b;
+    return SDC_OK;
+}
+
+sdc_status sdc_batch_accumulate(sdc_batch* b, const float* const* spins_dev, const int64_t* n_frames, void* stream) {
+    g_err.clear();
+    if (!b) return set_err(SDC_ERR_INVALID_ARG, "null batch");
+    if (!spins_dev || !n_frames) return set_err(SDC_ERR_INVALID_ARG, "null spins or frame counts");
+    const size_t n = b->plans.size();
+    for (size_t k = 0; k < n; ++k) {
+        sdc_status s = plan_usable(b->plans[k]);
+        if (s != SDC_OK) return s;
+        if (!spins_dev[k]) return set_err(SDC_ERR_INVALID_ARG, "null spins");
+        s = check_frames(b->plans[k], *b->sels[k], n_frames[k]);
+        if (s != SDC_OK) return s;
+    }
+    SDC_HIP(select_device(b->device), "hipSetDevice");
+    for (size_t k = 0; k < n; ++k) {
+        sdc_status s = queue_pack_self(b->plans[k], *b->sels[k], spins_dev[k], n_frames[k], stream, false);
+        if (s != SDC_OK) {
+            for (sdc_plan* p : b->plans) p->failed = true;
+            return s;
+        }
+    }
+    const int e = sdc::launch_fused_batch(b->bl, stream);
+    if (e != 0) {
+        for (sdc_plan* p : b->plans) p->failed = true;
+        return hip_err(e, "batched fused kernel");
+    }
+    return SDC_OK;
+}
+
+sdc_status sdc_batch_info(const sdc_batch* b, int64_t* n_tasks, int32_t* grid) {
+    g_err.clear();
+    if (!b) return set_err(SDC_ERR_INVALID_ARG, "null batch");
+    if (n_tasks) *n_tasks = b->bl.total;
+    if (grid) *grid = b->bl.grid;
+    return SDC_OK;
+}
+
+sdc_status sdc_batch_destroy(sdc_batch* b) {
+    g_err.clear();
+    if (!b) return SDC_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    delete b;
     return SDC_OK;
 }
 

@@ -169,6 +169,23 @@ struct FusedArgs {
 };
 int launch_fused(const FusedArgs& a, void* stream);
 
+// One persistent launch over the tasks of several plans (same precision and
+// bin class): args[n_plans] and task_start[n_plans + 1] in device memory,
+// queue = 8 device counters (zeroed by the launch itself).
+struct BatchLaunch {
+    const FusedArgs* args;
+    const int64_t* task_start;
+    int n_plans;
+    unsigned* queue;
+    int total;
+    int precision, radial;
+    int lds, grid;
+};
+int launch_fused_batch(const BatchLaunch& b, void* stream);
+// Workgroups that fit on the device at once (a multiple of 8, at most `total`
+// rounded up to 8); also sets the kernel's dynamic LDS limit.
+int batch_grid(int precision, int radial, int lds, int device, int total, int* grid);
+
 struct CountArgs {
     const KPair* pairs;
     const KStream* streams;
@@ -195,6 +212,7 @@ struct SelfArgs {
     int precision;        // split precisions: add the diagonal lo*lo term to H
     double* H;            // [n_lags][n_bins]; the i = j pairs all fall in bin 0
     int64_t n_bins;
+    double* norg;         // [n_lags] origin totals, += n_origins per selected lag
 };
 int launch_self(const SelfArgs& a, void* stream);
 
@@ -232,5 +250,11 @@ struct TrajArgs {
 int launch_traj(const TrajArgs& a, void* stream);
 
 int fused_lds_bytes(int win, int precision);
+// Largest dynamic LDS of a fused launch (the CU's 160 KB less room for the
+// batch kernel's few static words) and the self kernel's staging budget.
+constexpr int kMaxFusedLds = 160 * 1024 - 256;
+constexpr int64_t kSelfLdsBudget = 96 * 1024;
+// Set the kernels' dynamic-LDS limits on the current device.
+int prepare_kernels();
 
 }  // namespace sdc

@@ -264,25 +264,17 @@ int fused_lds_bytes(int win, int precision) {
     return lag_group(precision) * win * (int)sizeof(double) + 1024 * (int)sizeof(float);
 }
 
+// One task of a plan: the stream's tile pairs for one lag group, histogram
+// in LDS (`hist`: [LG][win] FP64, then the radial edge table), merged into
+// the plan's global bins at the end.  Called by the whole workgroup.
 template <int PREC, int RADIAL>
-__global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_kernel(FusedArgs a) {
+__device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double* hist) {
     constexpr int LG = lag_group(PREC);
     constexpr int NB = win_blocks(LG);
-    extern __shared__ double hist[];  // [LG][win] FP64, then radial edges
     float* e2s = (float*)(hist + LG * a.win);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1, h = lane >> 5, l32 = lane & 31;
-
-    // XCD-aware task order: consecutive tasks land on the same XCD (work-
-    // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
-    // the lag groups of one stream.  The workgroups running together on an
-    // XCD then walk the same tile pairs in step: they share the i-tile
-    // operand and overlapping time windows of the j-tile operand in L2.
-    const int n_tasks = a.n_groups * a.n_streams;
-    const int per = (n_tasks + 7) / 8;
-    const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (task >= n_tasks) return;
     const KGroup grp = a.groups[task % a.n_groups];
     const KStream st = a.streams[task / a.n_groups];
 
@@ -417,23 +409,91 @@ __global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_kern
     }
 }
 
+template <int PREC, int RADIAL>
+__global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_kernel(FusedArgs a) {
+    extern __shared__ double hist[];
+    // XCD-aware task order: consecutive tasks land on the same XCD (work-
+    // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
+    // the lag groups of one stream.  The workgroups running together on an
+    // XCD then walk the same tile pairs in step: they share the i-tile
+    // operand and overlapping time windows of the j-tile operand in L2.
+    const int n_tasks = a.n_groups * a.n_streams;
+    const int per = (n_tasks + 7) / 8;
+    const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (task >= n_tasks) return;
+    fused_task<PREC, RADIAL>(a, task, hist);
+}
+
+// Persistent kernel over the tasks of several plans (one launch for a
+// batch of samples).  The global task list (plan-major, then stream, then
+// lag group) is cut into 8 contiguous ranges, one queue per XCD; a
+// workgroup takes tasks from its own XCD's queue with an atomic counter and,
+// once that queue is empty, from the following queues in turn.  Every
+// counter only grows and each queue is visited until it is found empty, so
+// every workgroup leaves the loop after at most total + 8 claims.
+template <int PREC, int RADIAL>
+__global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_batch_kernel(
+    const FusedArgs* __restrict__ args, const int64_t* __restrict__ task_start, int n_plans,
+    unsigned* __restrict__ queue, int per, int total) {
+    extern __shared__ double hist[];
+    __shared__ int s_task, s_plan, s_queue, s_exhausted;
+    if (threadIdx.x == 0) {
+        s_queue = (int)(blockIdx.x % 8);
+        s_exhausted = 0;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) {
+            // queue state in LDS: no registers stay live across a task
+            int x = s_queue, exhausted = s_exhausted;
+            int t = -1;
+            while (exhausted < 8) {
+                const int lo = x * per;
+                const int hi = min(lo + per, total);
+                if (lo < hi) {
+                    const unsigned k = atomicAdd(&queue[x], 1u);
+                    if (k < (unsigned)(hi - lo)) {
+                        t = lo + (int)k;
+                        break;
+                    }
+                }
+                x = (x + 1) % 8;
+                ++exhausted;
+            }
+            int pl = 0;
+            if (t >= 0) {  // last plan whose first task is <= t
+                int lo = 0, hi = n_plans - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) / 2;
+                    if (task_start[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                pl = lo;
+                t -= (int)task_start[pl];
+            }
+            s_task = t;
+            s_plan = pl;
+            s_queue = x;
+            s_exhausted = exhausted;
+        }
+        __syncthreads();
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
+        const int pl = __builtin_amdgcn_readfirstlane(s_plan);
+        __syncthreads();
+        if (task < 0) break;
+        fused_task<PREC, RADIAL>(args[pl], task, hist);
+        __syncthreads();  // the histogram is reused by the next task
+    }
+}
+
 template <int PREC>
 static int launch_fused_prec(const FusedArgs& a, hipStream_t s) {
     const int lds = fused_lds_bytes(a.win, PREC);
     const int n_tasks = a.n_groups * a.n_streams;
     const int grid = 8 * ((n_tasks + 7) / 8);
-    hipError_t e;
-    if (a.kind == SDC_BINS_RADIAL) {
-        e = hipFuncSetAttribute((const void*)fused_kernel<PREC, 1>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return (int)e;
+    if (a.kind == SDC_BINS_RADIAL)
         hipLaunchKernelGGL((fused_kernel<PREC, 1>), dim3(grid), dim3(256), lds, s, a);
-    } else {
-        e = hipFuncSetAttribute((const void*)fused_kernel<PREC, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return (int)e;
+    else
         hipLaunchKernelGGL((fused_kernel<PREC, 0>), dim3(grid), dim3(256), lds, s, a);
-    }
     return (int)hipGetLastError();
 }
 
@@ -446,6 +506,66 @@ int launch_fused(const FusedArgs& a, void* stream) {
         case SDC_PREC_SPLIT_FP16: return launch_fused_prec<SDC_PREC_SPLIT_FP16>(a, s);
         default: return (int)hipErrorInvalidValue;
     }
+}
+
+template <int PREC, int RADIAL>
+static const void* batch_fn() {
+    return (const void*)fused_batch_kernel<PREC, RADIAL>;
+}
+
+static const void* batch_kernel_of(int precision, int radial) {
+    switch (precision) {
+        case SDC_PREC_FP32: return radial ? batch_fn<SDC_PREC_FP32, 1>() : batch_fn<SDC_PREC_FP32, 0>();
+        case SDC_PREC_SPLIT_BF16:
+            return radial ? batch_fn<SDC_PREC_SPLIT_BF16, 1>() : batch_fn<SDC_PREC_SPLIT_BF16, 0>();
+        case SDC_PREC_SPLIT_FP16:
+            return radial ? batch_fn<SDC_PREC_SPLIT_FP16, 1>() : batch_fn<SDC_PREC_SPLIT_FP16, 0>();
+        default: return nullptr;
+    }
+}
+
+int batch_grid(int precision, int radial, int lds, int device, int total, int* grid) {
+    const void* fn = batch_kernel_of(precision, radial);
+    if (!fn) return (int)hipErrorInvalidValue;
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+    if (e != hipSuccess) return (int)e;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return (int)e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = (int64_t)per_cu * n_cu;
+    if (g > total) g = total;
+    g = 8 * ((g + 7) / 8);
+    *grid = (int)(g < 8 ? 8 : g);
+    return 0;
+}
+
+int launch_fused_batch(const BatchLaunch& b, void* stream) {
+    if (b.total == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    int e = launch_zero(b.queue, 8 * sizeof(unsigned), stream);
+    if (e != 0) return e;
+    const int per = (b.total + 7) / 8;
+#define SDC_BATCH(P, R)                                                                                      \
+    hipLaunchKernelGGL((fused_batch_kernel<P, R>), dim3(b.grid), dim3(256), b.lds, s, b.args, b.task_start, \
+                       b.n_plans, b.queue, per, b.total)
+    switch (b.precision) {
+        case SDC_PREC_FP32:
+            if (b.radial) SDC_BATCH(SDC_PREC_FP32, 1);
+            else SDC_BATCH(SDC_PREC_FP32, 0);
+            break;
+        case SDC_PREC_SPLIT_BF16:
+            if (b.radial) SDC_BATCH(SDC_PREC_SPLIT_BF16, 1);
+            else SDC_BATCH(SDC_PREC_SPLIT_BF16, 0);
+            break;
+        case SDC_PREC_SPLIT_FP16:
+            if (b.radial) SDC_BATCH(SDC_PREC_SPLIT_FP16, 1);
+            else SDC_BATCH(SDC_PREC_SPLIT_FP16, 0);
+            break;
+        default: return (int)hipErrorInvalidValue;
+    }
+#undef SDC_BATCH
+    return (int)hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -585,6 +705,10 @@ __global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_blo
         }
     }
     __syncthreads();
+    // origin totals live on the device so that replays of a captured
+    // accumulate count their origins too
+    if (blockIdx.x == 0)
+        for (int l = tid; l < a.n_sel; l += 256) a.norg[a.lags[l]] += (double)a.n_origins;
     for (int l = tid; l < a.n_sel; l += 256) {
         unsafeAtomicAdd(&a.self[a.lags[l]], part[l]);
         if constexpr (PREC != SDC_PREC_FP32) unsafeAtomicAdd(&a.H[(int64_t)a.lags[l] * a.n_bins], part_lo[l]);
@@ -609,25 +733,43 @@ static void launch_self_kind(const SelfArgs& a, dim3 grid, int lds, hipStream_t 
 int launch_self(const SelfArgs& a, void* stream) {
     if (a.n_sel == 0) return 0;
     if (a.n_sel > 1024) return (int)hipErrorInvalidValue;
-    const int64_t budget = 96 * 1024;
+    const int64_t budget = kSelfLdsBudget;
     const int64_t per_site = a.t_need * 3 * (int64_t)sizeof(float);
     hipStream_t s = (hipStream_t)stream;
     if (per_site <= budget) {
         int spb = (int)(budget / per_site);
         if (spb > 16) spb = 16;
         const int lds = (int)(a.t_need * spb * 3 * sizeof(float));
-        const void* fns[3] = {(const void*)self_kernel<true, SDC_PREC_FP32>,
-                              (const void*)self_kernel<true, SDC_PREC_SPLIT_BF16>,
-                              (const void*)self_kernel<true, SDC_PREC_SPLIT_FP16>};
-        for (const void* f : fns) {
-            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e != hipSuccess) return (int)e;
-        }
         launch_self_kind<true>(a, dim3((unsigned)((a.n + spb - 1) / spb)), lds, s, spb);
     } else {
         launch_self_kind<false>(a, dim3((unsigned)((a.n + 15) / 16)), 0, s, 16);
     }
     return (int)hipGetLastError();
+}
+
+// Dynamic-LDS limits of every kernel that takes more than the default, set
+// once per device at plan creation so that the launch paths make no attribute
+// calls (they stay legal under stream capture).
+int prepare_kernels() {
+    const void* fused[] = {
+        (const void*)fused_kernel<SDC_PREC_FP32, 0>,        (const void*)fused_kernel<SDC_PREC_FP32, 1>,
+        (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0>,  (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1>,
+        (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0>,  (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1>,
+        batch_fn<SDC_PREC_FP32, 0>(),                       batch_fn<SDC_PREC_FP32, 1>(),
+        batch_fn<SDC_PREC_SPLIT_BF16, 0>(),                 batch_fn<SDC_PREC_SPLIT_BF16, 1>(),
+        batch_fn<SDC_PREC_SPLIT_FP16, 0>(),                 batch_fn<SDC_PREC_SPLIT_FP16, 1>()};
+    for (const void* f : fused) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxFusedLds);
+        if (e != hipSuccess) return (int)e;
+    }
+    const void* self[] = {(const void*)self_kernel<true, SDC_PREC_FP32>,
+                          (const void*)self_kernel<true, SDC_PREC_SPLIT_BF16>,
+                          (const void*)self_kernel<true, SDC_PREC_SPLIT_FP16>};
+    for (const void* f : self) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSelfLdsBudget);
+        if (e != hipSuccess) return (int)e;
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -52,7 +52,8 @@ class TrajSpec(ctypes.Structure):
 
 EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize", "sdc_plan_raw",
            "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset", "sdc_plan_destroy",
-           "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate")
+           "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate",
+           "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_info", "sdc_batch_destroy")
 FLAG_TIMING = 1
 
 _lib = None
@@ -83,11 +84,13 @@ def lib():
         L.sdc_last_error.restype = ctypes.c_char_p
         L.sdc_layout_keys.argtypes = [P, i64, ctypes.POINTER(BinSpec), P]
         L.sdc_traj_generate.argtypes = [P, i64, ctypes.POINTER(TrajSpec), P, i64, ctypes.c_int, P]
-        for name in ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize",
-                     "sdc_plan_raw", "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset",
-                     "sdc_plan_destroy",
-                     "sdc_layout_keys", "sdc_traj_generate"):
-            getattr(L, name).restype = ctypes.c_int
+        L.sdc_batch_create.argtypes = [P, i32, ctypes.POINTER(P)]
+        L.sdc_batch_accumulate.argtypes = [P, P, P, P]
+        L.sdc_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+        L.sdc_batch_destroy.argtypes = [P]
+        for name in EXPORTS:
+            if name not in ("sdc_status_string", "sdc_last_error"):
+                getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -237,6 +240,54 @@ class Plan:
     def close(self):
         if self._h is not None:
             _check(lib().sdc_plan_destroy(self._h), "sdc_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Several plans accumulated with one persistent fused launch (all lags)."""
+
+    def __init__(self, plans):
+        self._h = None
+        self.plans = list(plans)  # keeps the plans alive while the batch exists
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().sdc_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.plans), ctypes.byref(h)),
+               "sdc_batch_create")
+        self._h = h
+
+    def accumulate(self, spins_list, stream=None):
+        """spins_list[k]: contiguous float32 device tensor [T_k][N_k][3] for plan k."""
+        if len(spins_list) != len(self.plans):
+            raise ValueError("one trajectory per plan")
+        for p, sp in zip(self.plans, spins_list):
+            if tuple(sp.shape[1:]) != (p.n_sites, 3):
+                raise ValueError("spins must have shape [T][n_sites][3]")
+        ptrs = (ctypes.c_void_p * len(spins_list))(*[_dev_ptr(sp, "torch.float32").value for sp in spins_list])
+        nf = np.ascontiguousarray([sp.shape[0] for sp in spins_list], dtype=np.int64)
+        _check(lib().sdc_batch_accumulate(self._h, ctypes.cast(ptrs, ctypes.c_void_p), _np_ptr(nf),
+                                          _stream_ptr(stream)), "sdc_batch_accumulate")
+
+    def info(self):
+        """(total fused tasks, persistent grid size)."""
+        nt, g = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().sdc_batch_info(self._h, ctypes.byref(nt), ctypes.byref(g)), "sdc_batch_info")
+        return int(nt.value), int(g.value)
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().sdc_batch_destroy(self._h), "sdc_batch_destroy")
             self._h = None
 
     def __del__(self):

@@ -113,6 +113,18 @@ def test_validation_codes():
     assert sdc.lib().sdc_plan_n_bins(None, ctypes.byref(nb)) == sdc.ERR_INVALID_ARG
     for s in range(7):
         assert sdc.status_string(s)
+    # batch calls
+    L = sdc.lib()
+    hb = ctypes.c_void_p()
+    one = (ctypes.c_void_p * 1)(None)
+    assert L.sdc_batch_create(None, 1, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(ctypes.cast(one, ctypes.c_void_p), 1, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(ctypes.cast(one, ctypes.c_void_p), 0, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(ctypes.cast(one, ctypes.c_void_p), 1, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    assert not hb.value
+    assert L.sdc_batch_accumulate(None, None, None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_info(None, None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_destroy(None) == sdc.OK
 
 
 def test_no_device_reported_on_host():

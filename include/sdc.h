@@ -149,7 +149,11 @@ sdc_status sdc_accumulate(sdc_plan* plan, const float* spins_dev, int64_t n_fram
  * copy to host buffers and synchronise the stream.  Any output may be NULL.
  *  C_host      : [n_lags][n_bins]  H / (n_org[t] * count[b]), 0 if either is 0
  *  counts_host : [n_bins] exact ordered-pair counts (uint64)
- *  Csum_host   : [n_lags]  sum_b H[t][b] / (N * n_org[t])
+ *  Csum_host   : [n_lags]  sum_b H[t][b] / (N * n_org[t]), evaluated as
+ *                sum_o M(o s).M(o s + t) / (N * n_org[t]) with M(f) = sum_i
+ *                S_i(f) in FP64 (the same quantity, an exact identity; it
+ *                keeps the per-pair rounding of the split products from
+ *                adding up over the N^2 pairs of the site sum)
  *  Cself_host  : [n_lags]  sum_o sum_i S_i(o s).S_i(o s + t) / (N * n_org[t])
  *  Ssum_host   : [n_lags][2] (re, im) of sum_t w_t Csum(t) exp(-2 pi i k t / n_lags)
  *  Sself_host  : [n_lags][2] same for Cself; w_t = (1 + cos(pi t / n_lags)) / 2
@@ -163,17 +167,17 @@ sdc_status sdc_finalize(sdc_plan* plan, double* C_host, uint64_t* counts_host,
 /*
  * Raw accumulated state (for exact comparisons and checkpointing): H
  * [n_lags][n_bins] FP64, per-lag origin totals [n_lags] FP64, raw self sums
- * [n_lags] FP64.  Any output may be NULL.  Synchronises the stream.
- * Errors: INVALID_ARG, STATE, HIP.
+ * [n_lags] FP64, raw site sums sum_o M.M [n_lags] FP64.  Any output may be
+ * NULL.  Synchronises the stream.  Errors: INVALID_ARG, STATE, HIP.
  */
 sdc_status sdc_plan_raw(sdc_plan* plan, double* H_host, double* n_org_host,
-                        double* self_host, void* stream);
+                        double* self_host, double* msum_host, void* stream);
 
 /* Replace the accumulated state with one saved by sdc_plan_raw (resume).
  * Synchronises the stream.  Errors: INVALID_ARG, STATE, HIP. */
 sdc_status sdc_plan_load_raw(sdc_plan* plan, const double* H_host,
                              const double* n_org_host, const double* self_host,
-                             void* stream);
+                             const double* msum_host, void* stream);
 
 /* Per-kernel durations (milliseconds) of the most recent sdc_accumulate of a
  * plan created with SDC_FLAG_TIMING: ms[0] pack, ms[1] self term, ms[2] fused
@@ -199,13 +203,16 @@ typedef struct sdc_batch sdc_batch;
  *  plans   : n_plans distinct plans on one device, same precision, all
  *            periodic or all radial; each keeps its own bins, counts and
  *            origin totals.  Every lag of every plan is accumulated.
+ *  flags   : 0 or SDC_FLAG_TIMING (HIP events around the pack/self kernels
+ *            and around the fused launch, read by sdc_batch_timings; a
+ *            timing batch is meant for eager calls, not for capture).
  *  out     : receives the batch; it refers to the plans, which must outlive
  *            it (sdc_plan_destroy refuses a plan still in a batch).
  * Uploads the per-plan kernel arguments once.  Errors: INVALID_ARG,
  * UNSUPPORTED (more than 2^30 tasks), STATE (a plan failed earlier), OOM,
  * HIP.
  */
-sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, sdc_batch** out);
+sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t flags, sdc_batch** out);
 
 /*
  * Accumulate one trajectory per plan, all lags (as sdc_accumulate with
@@ -222,6 +229,12 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, sdc_batch**
  */
 sdc_status sdc_batch_accumulate(sdc_batch* batch, const float* const* spins_dev,
                                 const int64_t* n_frames, void* stream);
+
+/* Durations (milliseconds) of the most recent sdc_batch_accumulate of a
+ * batch created with SDC_FLAG_TIMING: ms[0] the pack and self kernels of all
+ * plans, ms[1] the persistent fused launch.  Waits for those events.
+ * Errors: INVALID_ARG, STATE (flag not set or no accumulate yet), HIP. */
+sdc_status sdc_batch_timings(sdc_batch* batch, double* ms);
 
 /* Total fused tasks of the batch and the persistent grid (workgroups).
  * Either output may be NULL.  Errors: INVALID_ARG. */

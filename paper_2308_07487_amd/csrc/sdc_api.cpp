@@ -117,6 +117,8 @@ struct sdc_plan {
     double* d_H = nullptr;
     double* d_self = nullptr;
     double* d_norg = nullptr;
+    double* d_msum = nullptr;    // [n_lags] sum_o M . M (site-summed raw correlation)
+    double* d_mframe = nullptr;  // [t_req][3] per-frame site sums (scratch)
     double* d_C = nullptr;
     double* d_fin = nullptr;  // csum, cself, ssum[2], sself[2]
     void* d_A = nullptr;
@@ -283,6 +285,8 @@ sdc_status queue_pack_self(sdc_plan* p, const LagSel& sel, const float* spins_de
     sa.H = p->d_H;
     sa.n_bins = L.n_bins;
     sa.norg = p->d_norg;
+    sa.mframe = p->d_mframe;
+    sa.msum = p->d_msum;
     if (timing) SDC_HIP(hipEventRecord(p->ev[1], hs), "hipEventRecord");
     e = sdc::launch_self(sa, stream);
     if (e != 0) {
@@ -300,7 +304,12 @@ struct sdc_batch {
     std::vector<const LagSel*> sels;
     std::vector<void*> owned;
     sdc::BatchLaunch bl{};
+    int flags = 0;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
     ~sdc_batch() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         for (sdc_plan* p : plans) --p->batch_refs;
         for (void* q : owned) (void)hipFree(q);
     }
@@ -459,6 +468,8 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     TRY(dalloc(&p->d_H, (size_t)corr->n_lags * L.n_bins, &p->owned));
     TRY(dalloc(&p->d_self, (size_t)corr->n_lags, &p->owned));
     TRY(dalloc(&p->d_norg, (size_t)corr->n_lags, &p->owned));
+    TRY(dalloc(&p->d_msum, (size_t)corr->n_lags, &p->owned));
+    TRY(dalloc(&p->d_mframe, (size_t)p->t_req * 3, &p->owned));
     TRY(dalloc(&p->d_fin, (size_t)6 * corr->n_lags, &p->owned));
     TRY(dalloc((char**)&p->d_A, p->bytes_A, &p->owned));
     TRY(dalloc((char**)&p->d_B, p->bytes_B, &p->owned));
@@ -478,6 +489,7 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     TRYHIP(hipMemset(p->d_H, 0, (size_t)corr->n_lags * L.n_bins * 8), "zero H");
     TRYHIP(hipMemset(p->d_self, 0, (size_t)corr->n_lags * 8), "zero self");
     TRYHIP(hipMemset(p->d_norg, 0, (size_t)corr->n_lags * 8), "zero origin totals");
+    TRYHIP(hipMemset(p->d_msum, 0, (size_t)corr->n_lags * 8), "zero site sums");
 
     sdc::CountArgs ca{};
     ca.pairs = p->d_pairs;
@@ -566,6 +578,7 @@ sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, doub
     fa.counts = p->d_counts;
     fa.n_org = p->d_norg;
     fa.self = p->d_self;
+    fa.msum = p->d_msum;
     fa.n_bins = L.n_bins;
     fa.n_sites = L.n;
     fa.n_lags = nl;
@@ -598,7 +611,8 @@ sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, doub
     return SDC_OK;
 }
 
-sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double* self_host, void* stream) {
+sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double* self_host, double* msum_host,
+                        void* stream) {
     g_err.clear();
     sdc_status s = plan_usable(p);
     if (s != SDC_OK) return s;
@@ -610,6 +624,8 @@ sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double*
     if (self_host) SDC_HIP(hipMemcpyAsync(self_host, p->d_self, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy self");
     if (n_org_host)
         SDC_HIP(hipMemcpyAsync(n_org_host, p->d_norg, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy origin totals");
+    if (msum_host)
+        SDC_HIP(hipMemcpyAsync(msum_host, p->d_msum, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy site sums");
     hipError_t se = hipStreamSynchronize(hs);
     if (se != hipSuccess) {
         p->failed = true;
@@ -619,11 +635,11 @@ sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double*
 }
 
 sdc_status sdc_plan_load_raw(sdc_plan* p, const double* H_host, const double* n_org_host, const double* self_host,
-                             void* stream) {
+                             const double* msum_host, void* stream) {
     g_err.clear();
     sdc_status s = plan_usable(p);
     if (s != SDC_OK) return s;
-    if (!H_host || !n_org_host || !self_host) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    if (!H_host || !n_org_host || !self_host || !msum_host) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
     const int nl = p->corr.n_lags;
     for (int t = 0; t < nl; ++t)
         if (!(n_org_host[t] >= 0.0)) return set_err(SDC_ERR_INVALID_ARG, "negative or NaN origin total");
@@ -632,6 +648,7 @@ sdc_status sdc_plan_load_raw(sdc_plan* p, const double* H_host, const double* n_
     SDC_HIP(hipMemcpyAsync(p->d_H, H_host, (size_t)nl * p->lay.n_bins * 8, hipMemcpyHostToDevice, hs), "load H");
     SDC_HIP(hipMemcpyAsync(p->d_self, self_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load self");
     SDC_HIP(hipMemcpyAsync(p->d_norg, n_org_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load origin totals");
+    SDC_HIP(hipMemcpyAsync(p->d_msum, msum_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load site sums");
     hipError_t se = hipStreamSynchronize(hs);
     if (se != hipSuccess) {
         p->failed = true;
@@ -664,6 +681,7 @@ sdc_status sdc_plan_reset(sdc_plan* p, void* stream) {
     int e = sdc::launch_zero(p->d_H, (int64_t)p->corr.n_lags * p->lay.n_bins * 8, stream);
     if (e == 0) e = sdc::launch_zero(p->d_self, (int64_t)p->corr.n_lags * 8, stream);
     if (e == 0) e = sdc::launch_zero(p->d_norg, (int64_t)p->corr.n_lags * 8, stream);
+    if (e == 0) e = sdc::launch_zero(p->d_msum, (int64_t)p->corr.n_lags * 8, stream);
     if (e != 0) {
         p->failed = true;
         return hip_err(e, "reset");
@@ -681,11 +699,12 @@ sdc_status sdc_plan_destroy(sdc_plan* p) {
     return SDC_OK;
 }
 
-sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, sdc_batch** out) {
+sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t flags, sdc_batch** out) {
     g_err.clear();
     if (!out) return set_err(SDC_ERR_INVALID_ARG, "null output pointer");
     *out = nullptr;
     if (!plans) return set_err(SDC_ERR_INVALID_ARG, "null plan list");
+    if ((flags & ~SDC_FLAG_TIMING) != 0) return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
     if (n_plans < 1 || n_plans > 4096) return set_err(SDC_ERR_INVALID_ARG, "n_plans must be in [1, 4096]");
     for (int k = 0; k < n_plans; ++k) {
         sdc_status s = plan_usable(plans[k]);
@@ -709,6 +728,16 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, sdc_batch**
         return set_err(SDC_ERR_OOM, "host allocation failed");
     }
     b->device = device;
+    b->flags = flags;
+    if (flags & SDC_FLAG_TIMING) {
+        for (hipEvent_t& e : b->ev) {
+            const hipError_t he = hipEventCreate(&e);
+            if (he != hipSuccess) {
+                delete b;
+                return hip_err((int)he, "hipEventCreate");
+            }
+        }
+    }
     std::vector<sdc::FusedArgs> args((size_t)n_plans);
     std::vector<int64_t> start((size_t)n_plans + 1, 0);
     int lds = 0;
@@ -779,6 +808,9 @@ sdc_status sdc_batch_accumulate(sdc_batch* b, const float* const* spins_dev, con
         if (s != SDC_OK) return s;
     }
     SDC_HIP(select_device(b->device), "hipSetDevice");
+    const bool timing = (b->flags & SDC_FLAG_TIMING) != 0;
+    hipStream_t hs = (hipStream_t)stream;
+    if (timing) SDC_HIP(hipEventRecord(b->ev[0], hs), "hipEventRecord");
     for (size_t k = 0; k < n; ++k) {
         sdc_status s = queue_pack_self(b->plans[k], *b->sels[k], spins_dev[k], n_frames[k], stream, false);
         if (s != SDC_OK) {
@@ -786,10 +818,29 @@ sdc_status sdc_batch_accumulate(sdc_batch* b, const float* const* spins_dev, con
             return s;
         }
     }
+    if (timing) SDC_HIP(hipEventRecord(b->ev[1], hs), "hipEventRecord");
     const int e = sdc::launch_fused_batch(b->bl, stream);
     if (e != 0) {
         for (sdc_plan* p : b->plans) p->failed = true;
         return hip_err(e, "batched fused kernel");
+    }
+    if (timing) {
+        SDC_HIP(hipEventRecord(b->ev[2], hs), "hipEventRecord");
+        b->timed = true;
+    }
+    return SDC_OK;
+}
+
+sdc_status sdc_batch_timings(sdc_batch* b, double* ms) {
+    g_err.clear();
+    if (!b || !ms) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    if (!(b->flags & SDC_FLAG_TIMING) || !b->timed)
+        return set_err(SDC_ERR_STATE, "no timed batch accumulate (create the batch with SDC_FLAG_TIMING)");
+    SDC_HIP(hipEventSynchronize(b->ev[2]), "hipEventSynchronize");
+    for (int k = 0; k < 2; ++k) {
+        float t = 0.0f;
+        SDC_HIP(hipEventElapsedTime(&t, b->ev[k], b->ev[k + 1]), "hipEventElapsedTime");
+        ms[k] = t;
     }
     return SDC_OK;
 }

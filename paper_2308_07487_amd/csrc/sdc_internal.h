@@ -213,6 +213,8 @@ struct SelfArgs {
     double* H;            // [n_lags][n_bins]; the i = j pairs all fall in bin 0
     int64_t n_bins;
     double* norg;         // [n_lags] origin totals, += n_origins per selected lag
+    double* mframe;       // [t_need][3] scratch: site-summed spin of each frame
+    double* msum;         // [n_lags] += sum_o M(o s) . M(o s + t)
 };
 int launch_self(const SelfArgs& a, void* stream);
 
@@ -221,6 +223,7 @@ struct FinalArgs {
     const unsigned long long* counts;
     const double* n_org;   // device [n_lags]
     const double* self;    // device [n_lags]
+    const double* msum;    // device [n_lags] site-summed raw correlation
     int64_t n_bins, n_sites;
     int n_lags;
     double* C;             // [n_lags][n_bins] or null

@@ -730,6 +730,47 @@ static void launch_self_kind(const SelfArgs& a, dim3 grid, int lds, hipStream_t 
     }
 }
 
+// Site-summed spin M(f) = sum_i S_i(f) of every frame the accumulate reads,
+// in FP64: one workgroup per frame.
+__global__ __launch_bounds__(256) void magnet_kernel(const float* __restrict__ frames, int64_t n,
+                                                     double* __restrict__ M) {
+    __shared__ double red[3][256];
+    const int64_t f = blockIdx.x;
+    const float* x = frames + f * n * 3;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        s0 += (double)x[3 * i];
+        s1 += (double)x[3 * i + 1];
+        s2 += (double)x[3 * i + 2];
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    red[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) M[f * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Site-summed correlation of each selected lag: the sum over all ordered
+// pairs of S_i(o s) . S_j(o s + t) equals M(o s) . M(o s + t), summed over
+// the origins in FP64 (one thread per lag).
+__global__ __launch_bounds__(256) void msum_kernel(SelfArgs a) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= a.n_sel) return;
+    const int t = a.lags[l];
+    double s = 0.0;
+    for (int o = 0; o < a.n_origins; ++o) {
+        const double* m0 = a.mframe + (int64_t)o * a.stride * 3;
+        const double* m1 = m0 + (int64_t)t * 3;
+        s += m0[0] * m1[0] + m0[1] * m1[1] + m0[2] * m1[2];
+    }
+    a.msum[t] += s;
+}
+
 int launch_self(const SelfArgs& a, void* stream) {
     if (a.n_sel == 0) return 0;
     if (a.n_sel > 1024) return (int)hipErrorInvalidValue;
@@ -744,6 +785,8 @@ int launch_self(const SelfArgs& a, void* stream) {
     } else {
         launch_self_kind<false>(a, dim3((unsigned)((a.n + 15) / 16)), 0, s, 16);
     }
+    hipLaunchKernelGGL(magnet_kernel, dim3((unsigned)a.t_need), dim3(256), 0, s, a.frames, a.n, a.mframe);
+    hipLaunchKernelGGL(msum_kernel, dim3((unsigned)((a.n_sel + 255) / 256)), dim3(256), 0, s, a);
     return (int)hipGetLastError();
 }
 
@@ -787,22 +830,16 @@ __global__ void normalize_kernel(FinalArgs a) {
     }
 }
 
+// Site-summed and self correlations per lag.  The site sum comes from the
+// magnetisation products (an exact identity for the sum of H over all
+// bins), which keeps the per-bin rounding of the reduced-precision products
+// from adding up over N^2 pairs.
 __global__ __launch_bounds__(256) void sums_kernel(FinalArgs a) {
-    __shared__ double red[256];
-    const int t = blockIdx.x;
-    double s = 0.0;
-    for (int64_t b = threadIdx.x; b < a.n_bins; b += 256) s += a.H[(int64_t)t * a.n_bins + b];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double d = (double)a.n_sites * a.n_org[t];
-        a.csum[t] = d > 0.0 ? red[0] / d : 0.0;
-        a.cself[t] = d > 0.0 ? a.self[t] / d : 0.0;
-    }
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_lags) return;
+    const double d = (double)a.n_sites * a.n_org[t];
+    a.csum[t] = d > 0.0 ? a.msum[t] / d : 0.0;
+    a.cself[t] = d > 0.0 ? a.self[t] / d : 0.0;
 }
 
 __global__ void dft_kernel(FinalArgs a) {
@@ -834,7 +871,7 @@ int launch_finalize(const FinalArgs& a, void* stream) {
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(sums_kernel, dim3(a.n_lags), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sums_kernel, dim3((a.n_lags + 255) / 256), dim3(256), 0, s, a);
     hipLaunchKernelGGL(dft_kernel, dim3((a.n_lags + 63) / 64), dim3(64), 0, s, a);
     return (int)hipGetLastError();
 }

@@ -15,6 +15,9 @@ Workload recipes (lattice constant 1, unit spins, fp32 xyz):
   that every product and every partial sum up to 2^24 units is exact in FP32.
 - ``static_frames``: every spin along one fixed axis in every frame.
 - ``spiral_frames``: a planted spin wave with a commensurate wave vector.
+- ``batch_samples``: the recipe of a batch of independent samples (lattice,
+  box edge, origin and lag counts, seeds), as the paper's averages over many
+  realizations of different lattices need.
 """
 from __future__ import annotations
 
@@ -82,6 +85,25 @@ def spiral_frames(pos, q, theta, omega, n_frames, dt):
     s, c = np.sin(theta), np.cos(theta)
     out = np.stack([s * np.cos(phi), s * np.sin(phi), np.full_like(phi, c)], axis=-1)
     return out.astype(np.float32)
+
+
+def batch_samples(n_samples=48, seed=0x5DC00500, edge=(10, 40), origins=(32, 128), lags=(64, 256)):
+    """Sample m: sc for even m, bcc for odd m; cubic box edge uniform in
+    `edge` (the first sample takes the smallest edge, the last the largest),
+    origin and lag counts uniform in `origins` and `lags`, trajectory seed
+    seed + m.  Returns a list of dicts (lattice, cells, n_origins, n_lags, seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for m in range(n_samples):
+        L = int(rng.integers(edge[0], edge[1] + 1))
+        if m == 0:
+            L = edge[0]
+        elif m == n_samples - 1:
+            L = edge[1]
+        out.append(dict(lattice="sc" if m % 2 == 0 else "bcc", cells=(L, L, L),
+                        n_origins=int(rng.integers(origins[0], origins[1] + 1)),
+                        n_lags=int(rng.integers(lags[0], lags[1] + 1)), seed=seed + m))
+    return out
 
 
 def permute_sites(pos, frames, seed):

@@ -53,7 +53,8 @@ class TrajSpec(ctypes.Structure):
 EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize", "sdc_plan_raw",
            "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset", "sdc_plan_destroy",
            "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate",
-           "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_info", "sdc_batch_destroy")
+           "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_timings", "sdc_batch_info",
+           "sdc_batch_destroy")
 FLAG_TIMING = 1
 
 _lib = None
@@ -73,8 +74,8 @@ def lib():
         L.sdc_plan_n_bins.argtypes = [P, ctypes.POINTER(i64)]
         L.sdc_accumulate.argtypes = [P, P, i64, P, i32, P]
         L.sdc_finalize.argtypes = [P, P, P, P, P, P, P, P]
-        L.sdc_plan_raw.argtypes = [P, P, P, P, P]
-        L.sdc_plan_load_raw.argtypes = [P, P, P, P, P]
+        L.sdc_plan_raw.argtypes = [P, P, P, P, P, P]
+        L.sdc_plan_load_raw.argtypes = [P, P, P, P, P, P]
         L.sdc_plan_timings.argtypes = [P, P]
         L.sdc_plan_reset.argtypes = [P, P]
         L.sdc_plan_destroy.argtypes = [P]
@@ -84,7 +85,8 @@ def lib():
         L.sdc_last_error.restype = ctypes.c_char_p
         L.sdc_layout_keys.argtypes = [P, i64, ctypes.POINTER(BinSpec), P]
         L.sdc_traj_generate.argtypes = [P, i64, ctypes.POINTER(TrajSpec), P, i64, ctypes.c_int, P]
-        L.sdc_batch_create.argtypes = [P, i32, ctypes.POINTER(P)]
+        L.sdc_batch_create.argtypes = [P, i32, i32, ctypes.POINTER(P)]
+        L.sdc_batch_timings.argtypes = [P, P]
         L.sdc_batch_accumulate.argtypes = [P, P, P, P]
         L.sdc_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.sdc_batch_destroy.argtypes = [P]
@@ -213,19 +215,22 @@ class Plan:
                     Sself=sf[:, 0] + 1j * sf[:, 1])
 
     def raw(self, stream=None):
-        """(H [n_lags][n_bins], n_org [n_lags], self [n_lags]) as accumulated (FP64)."""
+        """(H [n_lags][n_bins], n_org [n_lags], self [n_lags], msum [n_lags]) as
+        accumulated (FP64); msum = sum over origins of M(o s).M(o s + t)."""
         H = np.zeros((self.n_lags, self.n_bins))
         no = np.zeros(self.n_lags)
         sf = np.zeros(self.n_lags)
-        _check(lib().sdc_plan_raw(self._h, _np_ptr(H), _np_ptr(no), _np_ptr(sf), _stream_ptr(stream)),
-               "sdc_plan_raw")
-        return H, no, sf
+        ms = np.zeros(self.n_lags)
+        _check(lib().sdc_plan_raw(self._h, _np_ptr(H), _np_ptr(no), _np_ptr(sf), _np_ptr(ms),
+                                  _stream_ptr(stream)), "sdc_plan_raw")
+        return H, no, sf, ms
 
-    def load_raw(self, H, n_org, self_raw, stream=None):
+    def load_raw(self, H, n_org, self_raw, msum, stream=None):
         H = np.ascontiguousarray(H, dtype=np.float64)
         n_org = np.ascontiguousarray(n_org, dtype=np.float64)
         self_raw = np.ascontiguousarray(self_raw, dtype=np.float64)
-        _check(lib().sdc_plan_load_raw(self._h, _np_ptr(H), _np_ptr(n_org), _np_ptr(self_raw),
+        msum = np.ascontiguousarray(msum, dtype=np.float64)
+        _check(lib().sdc_plan_load_raw(self._h, _np_ptr(H), _np_ptr(n_org), _np_ptr(self_raw), _np_ptr(msum),
                                        _stream_ptr(stream)), "sdc_plan_load_raw")
 
     def timings(self):
@@ -258,14 +263,20 @@ class Plan:
 class Batch:
     """Several plans accumulated with one persistent fused launch (all lags)."""
 
-    def __init__(self, plans):
+    def __init__(self, plans, timing=False):
         self._h = None
         self.plans = list(plans)  # keeps the plans alive while the batch exists
         arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         h = ctypes.c_void_p()
-        _check(lib().sdc_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.plans), ctypes.byref(h)),
-               "sdc_batch_create")
+        _check(lib().sdc_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.plans),
+                                      FLAG_TIMING if timing else 0, ctypes.byref(h)), "sdc_batch_create")
         self._h = h
+
+    def timings(self):
+        """(pack_and_self_ms, fused_ms) of the last accumulate (timing batches only)."""
+        ms = np.zeros(2)
+        _check(lib().sdc_batch_timings(self._h, _np_ptr(ms)), "sdc_batch_timings")
+        return float(ms[0]), float(ms[1])
 
     def accumulate(self, spins_list, stream=None):
         """spins_list[k]: contiguous float32 device tensor [T_k][N_k][3] for plan k."""

@@ -117,13 +117,16 @@ def test_validation_codes():
     L = sdc.lib()
     hb = ctypes.c_void_p()
     one = (ctypes.c_void_p * 1)(None)
-    assert L.sdc_batch_create(None, 1, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
-    assert L.sdc_batch_create(ctypes.cast(one, ctypes.c_void_p), 1, None) == sdc.ERR_INVALID_ARG
-    assert L.sdc_batch_create(ctypes.cast(one, ctypes.c_void_p), 0, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
-    assert L.sdc_batch_create(ctypes.cast(one, ctypes.c_void_p), 1, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    one_p = ctypes.cast(one, ctypes.c_void_p)
+    assert L.sdc_batch_create(None, 1, 0, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(one_p, 1, 0, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(one_p, 0, 0, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(one_p, 1, 0, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_create(one_p, 1, 4, ctypes.byref(hb)) == sdc.ERR_INVALID_ARG
     assert not hb.value
     assert L.sdc_batch_accumulate(None, None, None, None) == sdc.ERR_INVALID_ARG
     assert L.sdc_batch_info(None, None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_batch_timings(None, None) == sdc.ERR_INVALID_ARG
     assert L.sdc_batch_destroy(None) == sdc.OK
 
 

@@ -90,7 +90,7 @@ def test_batch_matches_oracle(torch_dev, S, orc, prec):
     for p, (pos, kind, fr, cells, n_o, n_L) in zip(plans, host):
         okind = orc.SC if kind == S.BINS_SC else orc.BCC
         out = p.finalize()
-        H, no, sf = p.raw()
+        H, no, sf, ms = p.raw()
         lags = np.arange(n_L)
         Hr, cr = orc.binned_corr(pos, fr, okind, n_o, lags, cells=cells)
         sfr = orc.self_corr(fr, n_o, lags)
@@ -115,7 +115,7 @@ def test_batch_dyadic_bit_exact(torch_dev, S, orc, prec):
         b.accumulate(frames)
     for p, (pos, kind, fr, cells, n_o, n_L) in zip(plans, host):
         okind = orc.SC if kind == S.BINS_SC else orc.BCC
-        H, no, _ = p.raw()
+        H, no, _, _ = p.raw()
         Hr, _ = orc.binned_corr(pos, fr, okind, n_o, np.arange(n_L), cells=cells)
         np.testing.assert_array_equal(H, Hr)
         p.close()
@@ -155,10 +155,11 @@ def test_batch_equals_single_plans(torch_dev, S):
     for p, fr in zip(plans_s, frames):
         p.accumulate(fr)
     for pb, ps in zip(plans_b, plans_s):
-        Hb, nob, sfb = pb.raw()
-        Hs, nos, sfs = ps.raw()
+        Hb, nob, sfb, msb = pb.raw()
+        Hs, nos, sfs, mss = ps.raw()
         np.testing.assert_array_equal(nob, nos)
         np.testing.assert_allclose(sfb, sfs, rtol=1e-12)  # FP64 atomics: order varies
+        np.testing.assert_array_equal(msb, mss)
         # same tasks, same FP32 sums; only the order of the FP64 merges differs
         np.testing.assert_allclose(Hb, Hs, rtol=1e-12, atol=1e-12 * np.max(np.abs(Hs)))
         pb.close()
@@ -195,7 +196,7 @@ def test_graph_capture_replays(torch_dev, S):
     torch.cuda.synchronize()
     # capture executes nothing
     for p in cap_plans + [single]:
-        _, no, _ = p.raw()
+        _, no, _, _ = p.raw()
         assert not no.any()
     x = torch.randn(512, 512, device="cuda")
     for rep in range(1, 4):
@@ -207,7 +208,7 @@ def test_graph_capture_replays(torch_dev, S):
         for k, p in enumerate(cap_plans + [single]):
             r = ref[k if k < len(cap_plans) else 0]
             out = p.finalize()
-            _, no, _ = p.raw()
+            _, no, _, _ = p.raw()
             n_o = samples[k if k < len(cap_plans) else 0][2]
             np.testing.assert_array_equal(no, float(rep * n_o))
             np.testing.assert_array_equal(out["counts"], r["counts"])

@@ -1,0 +1,168 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+bench times (all lags in one accumulate; the batch in one persistent launch).
+
+The oracle cannot evaluate every bin at these sizes, so each case checks
+- sampled bins at a lag subset against the FP64 oracle on the same fp32
+  frames (bins chosen at the corners of the range plus seeded random ones);
+- exact pair counts: every bin of a periodic lattice holds N ordered pairs
+  (Bravais lattice), the radial counts of the sampled shells equal the
+  oracle's and all shells sum to N^2;
+- on every bin at once, the site-sum identity sum_b H(b, t) =
+  sum_o M(t_o).M(t_o + t) with M = sum_i S_i (FP64 magnetisation).
+Inputs are the library's own seeded RK4 trajectories of each workload.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_07487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2308_07487_amd import sdc
+    return sdc
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _traj(torch, S, pos, kind, cells, T, **kw):
+    fr = torch.empty((T, pos.shape[0], 3), dtype=torch.float32, device="cuda")
+    S.traj_generate(pos, kind, fr, cells=cells, **kw)
+    torch.cuda.synchronize()
+    return fr
+
+
+def _sum_bar(prec, n_o):
+    """Bar of the site-sum identity: the sum runs over all N^2 pairs, so with
+    split-BF16 its unbiased rounding noise relative to C_sum ~ 1 does not
+    shrink with N, only with the origins: six standard deviations of
+    2^-17 / sqrt(n_o), and never looser than needed above 1e-6."""
+    if prec != "split_bf16":
+        return 1e-6
+    return max(1e-6, 6 * 2.0 ** -17 / np.sqrt(n_o))
+
+
+def _csum_identity(torch, fr, n_o, n_L, csum):
+    M = fr.double().sum(dim=1)
+    ref = torch.stack([(M[:n_o] * M[t:t + n_o]).sum() for t in range(n_L)]).cpu().numpy()
+    ref /= float(fr.shape[1]) * n_o
+    return float(np.max(np.abs(csum - ref)) / np.max(np.abs(ref)))
+
+
+def _sampled(orc, okind, pos, fr_host, n_o, lags, bins, C, counts, **spec):
+    Hs, cs = orc.binned_corr_select(pos, fr_host, okind, n_o, lags, bins, **spec)
+    np.testing.assert_array_equal(counts[bins], cs)
+    nz = cs > 0
+    ref = np.zeros_like(Hs)
+    ref[:, nz] = Hs[:, nz] / (n_o * cs[nz].astype(np.float64))
+    got = C[np.asarray(lags)][:, bins]
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def _periodic_case(torch, S, orc, L, J, init, sigma, seed, n_o, n_L, prec, bar, rng_seed):
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    fr = _traj(torch, S, pos, S.BINS_SC, L, n_o + n_L - 1, J=J, dt=0.01, init=init, sigma=sigma, seed=seed)
+    with S.Plan(pos, S.BINS_SC, n_o, n_L, prec, cells=L) as p:
+        p.accumulate(fr)
+        out = p.finalize()
+    np.testing.assert_array_equal(out["counts"], n)
+    ident = _csum_identity(torch, fr, n_o, n_L, out["Csum"])
+    rng = np.random.default_rng(rng_seed)
+    bins = np.unique(np.concatenate([[0, 1, n - 1], rng.choice(n, 40, replace=False)]))
+    lags = [0, 1, n_L // 2, n_L - 1]
+    e = _sampled(orc, orc.SC, pos, fr.cpu().numpy(), n_o, lags, bins, out["C"], out["counts"], cells=L)
+    print(f"  {prec}: sampled normwise error {e:.3e}, site-sum identity {ident:.3e}", flush=True)
+    assert e <= bar and ident <= max(bar, _sum_bar(prec, n_o))
+
+
+@pytest.mark.parametrize("prec,bar", [("split_fp16", 1e-6), ("split_bf16", 5e-5)])
+def test_sc32_fm_full(torch_dev, S, orc, prec, bar):
+    """sc 32^3 ferromagnet from a z-aligned start (sigma = 0.3): spins stay
+    nearly parallel, so split-BF16's rounding is coherent and only its
+    deterministic bound applies; split-FP16 meets 1e-6."""
+    _say(f"sc 32^3 FM full size {prec}")
+    _periodic_case(torch_dev, S, orc, (32, 32, 32), -1.0, S.INIT_PERTURBED_Z, 0.3, 0x5DC00001, 64, 256,
+                   prec, bar, 5)
+
+
+def test_sc36_afm_full(torch_dev, S, orc):
+    _say("sc 36^3 AFM full size split_bf16")
+    _periodic_case(torch_dev, S, orc, (36, 36, 36), 1.0, S.INIT_UNIFORM, 0.0, 0x5DC00002, 128, 256,
+                   "split_bf16", 1e-6, 6)
+
+
+def test_ball65k_radial_full(torch_dev, S, orc):
+    _say("ball of 65536 points, 1024 shells, full size split_bf16")
+    n, n_o, n_L, ns, rm = 65536, 64, 128, 1024, 50.0
+    pos = inputs.ball_positions(n, 25.0, seed=0x5DC00013)
+    fr = _traj(torch_dev, S, pos, S.BINS_RADIAL, (0, 0, 0), n_o + n_L - 1, J=1.0, dt=0.005,
+               coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5, init=S.INIT_UNIFORM, seed=0x5DC00003)
+    with S.Plan(pos, S.BINS_RADIAL, n_o, n_L, "split_bf16", n_shells=ns, r_max=rm) as p:
+        p.accumulate(fr)
+        out = p.finalize()
+    assert int(out["counts"].sum()) == n * n
+    assert out["counts"][0] >= n
+    ident = _csum_identity(torch_dev, fr, n_o, n_L, out["Csum"])
+    rng = np.random.default_rng(7)
+    bins = np.unique(np.concatenate([[0, 1, 2, 100, 400, 700, 1000, ns - 1], rng.choice(ns, 8, replace=False)]))
+    lags = [0, 1, n_L // 2, n_L - 1]
+    e = _sampled(orc, orc.RADIAL, pos, fr.cpu().numpy(), n_o, lags, bins, out["C"], out["counts"],
+                 n_shells=ns, r_max=rm)
+    print(f"  sampled normwise error {e:.3e}, site-sum identity {ident:.3e}", flush=True)
+    assert e <= 1e-6 and ident <= _sum_bar("split_bf16", n_o)
+
+
+def test_batch48_full(torch_dev, S, orc):
+    """48 samples in one persistent launch (sc / bcc, edges 10..40)."""
+    torch = torch_dev
+    specs = inputs.batch_samples(48, 0x5DC00500)
+    _say("batch of 48 samples, full size split_bf16")
+    plans, frames, host = [], [], []
+    for s in specs:
+        sc = s["lattice"] == "sc"
+        pos = inputs.sc_positions(s["cells"]) if sc else inputs.bcc_positions(s["cells"])
+        kind = S.BINS_SC if sc else S.BINS_BCC
+        fr = _traj(torch, S, pos, kind, s["cells"], s["n_origins"] + s["n_lags"] - 1, J=1.0, dt=0.01,
+                   coupling=S.COUPLING_NN_RANDOM_SIGN, init=S.INIT_UNIFORM, seed=s["seed"])
+        plans.append(S.Plan(pos, kind, s["n_origins"], s["n_lags"], "split_bf16", cells=s["cells"]))
+        frames.append(fr)
+        host.append((pos, kind))
+    print(f"  {len(plans)} plans created", flush=True)
+    with S.Batch(plans) as b:
+        b.accumulate(frames)
+        torch.cuda.synchronize()
+    print("  batch accumulated", flush=True)
+    order = np.argsort([h[0].shape[0] for h in host], kind="stable")
+    check = {int(order[0]), int(order[1]), int(order[len(order) // 2])}
+    worst_ident = 0.0  # identity error relative to each sample's own bar
+    for k, (p, s) in enumerate(zip(plans, specs)):
+        pos, kind = host[k]
+        n, n_o, n_L = pos.shape[0], s["n_origins"], s["n_lags"]
+        out = p.finalize(want_C=k in check)
+        np.testing.assert_array_equal(out["counts"], n)
+        worst_ident = max(worst_ident, _csum_identity(torch, frames[k], n_o, n_L, out["Csum"])
+                          / _sum_bar("split_bf16", n_o))
+        if k in check:
+            rng = np.random.default_rng(k)
+            bins = np.unique(np.concatenate([[0, 1, n - 1], rng.choice(n, 24, replace=False)]))
+            lags = sorted({0, 1, n_L // 2, n_L - 1})
+            okind = orc.SC if kind == S.BINS_SC else orc.BCC
+            e = _sampled(orc, okind, pos, frames[k].cpu().numpy(), n_o, lags, bins, out["C"], out["counts"],
+                         cells=s["cells"])
+            print(f"  sample {k} ({s['lattice']} {s['cells'][0]}, N={n}): sampled error {e:.3e}", flush=True)
+            assert e <= 1e-6
+        p.close()
+    print(f"  site-sum identity over all samples: {worst_ident:.3f} of the bar", flush=True)
+    assert worst_ident <= 1.0

@@ -44,7 +44,7 @@ def _run_gpu(torch, S, pos, frames, kind, n_o, n_L, prec, lags=None, stride=1, *
         d = torch.from_numpy(frames).cuda()
         p.accumulate(d, lags=lags)
         out = p.finalize()
-        H, no, sf = p.raw()
+        H, no, sf, ms = p.raw()
         torch.cuda.synchronize()
     return out, H, no, sf
 
@@ -182,13 +182,15 @@ def test_lag_subset_and_accumulation(torch_dev, S, orc):
     with S.Plan(pos, S.BINS_SC, n_o, n_L, "fp32", cells=L) as p:
         p.accumulate(torch_dev.from_numpy(fr1).cuda(), lags=lags)
         p.accumulate(torch_dev.from_numpy(fr2).cuda(), lags=lags[:2])
-        H, no, sf = p.raw()
+        H, no, sf, ms = p.raw()
         H1, c1 = orc.binned_corr(pos, fr1, orc.SC, n_o, lags, cells=L)
         H2, _ = orc.binned_corr(pos, fr2, orc.SC, n_o, lags[:2], cells=L)
         ref = np.zeros((n_L, pos.shape[0]))
         ref[lags] += H1
         ref[lags[:2]] += H2
         assert _normwise(H, ref) < 1e-6
+        # site sums: the magnetisation products equal the oracle's sum over bins
+        np.testing.assert_allclose(ms, ref.sum(axis=1), rtol=1e-10, atol=1e-10 * np.abs(ref).sum())
         expect_no = np.zeros(n_L)
         expect_no[lags] += n_o
         expect_no[lags[:2]] += n_o
@@ -198,12 +200,13 @@ def test_lag_subset_and_accumulation(torch_dev, S, orc):
         np.testing.assert_array_equal(out["C"][untouched], 0.0)
         # raw round trip and reset
         p.reset()
-        H0, no0, _ = p.raw()
-        assert not H0.any() and not no0.any()
-        p.load_raw(H, no, sf)
-        H3, no3, sf3 = p.raw()
+        H0, no0, _, ms0 = p.raw()
+        assert not H0.any() and not no0.any() and not ms0.any()
+        p.load_raw(H, no, sf, ms)
+        H3, no3, sf3, ms3 = p.raw()
         np.testing.assert_array_equal(H3, H)
         np.testing.assert_array_equal(no3, no)
+        np.testing.assert_array_equal(ms3, ms)
 
 
 def test_nan_propagates(torch_dev, S):

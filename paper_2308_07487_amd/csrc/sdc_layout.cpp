@@ -49,6 +49,29 @@ uint64_t spread3(uint64_t v) {
     return v;
 }
 
+// Cut every stream into consecutive segments of at most kStreamSegment pairs
+// (same window, same bins).  The lag groups of a segment run as neighbouring
+// tasks on one XCD and share its operands in L2 only while they are in step;
+// over a whole stream (up to ~1000 pairs) they drift apart and the operand
+// re-reads miss L2.  Segments of ~100 pairs cut the L2 misses ~3x at the
+// price of ~8x more histogram merges (still < 1% of the work).
+constexpr int kStreamSegment = 96;
+
+void split_streams(Layout* lay) {
+    std::vector<KStream> out;
+    for (const KStream& s : lay->streams) {
+        const int len = s.p1 - s.p0;
+        const int nseg = (len + kStreamSegment - 1) / kStreamSegment;
+        for (int k = 0; k < nseg; ++k) {
+            KStream t = s;
+            t.p0 = s.p0 + (int)((int64_t)k * len / nseg);
+            t.p1 = s.p0 + (int)((int64_t)(k + 1) * len / nseg);
+            out.push_back(t);
+        }
+    }
+    lay->streams.swap(out);
+}
+
 sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec, Layout* lay,
                           std::string* err) {
     const bool bcc = spec->kind == SDC_BINS_PERIODIC_BCC;
@@ -171,6 +194,7 @@ sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec,
                         s.p1 = (int32_t)lay->pairs.size();
                         lay->streams.push_back(s);
                     }
+    split_streams(lay);
     return SDC_OK;
 }
 

@@ -49,14 +49,20 @@ typedef enum {
  *  SPLIT_BF16  : x = hi + lo, hi = bf16(x), lo = bf16(x - hi); the product is
  *                hi*hi + hi*lo + lo*hi on BF16 MFMA (three products).
  *  SPLIT_FP16  : the same split with FP16 parts (about 22 significant bits).
- *  For both splits the omitted lo*lo product is added exactly (FP64) for the
- *  i = j pairs, where it would otherwise bias C at zero displacement; off the
- *  diagonal it is left out (unbiased rounding noise, <= 2^-16 (BF16) or
- *  2^-22 (FP16) of |S_i||S_j| per term). */
+ *  BF16X3      : x = hi + mid + lo in BF16 (exact for normal fp32 x); the
+ *                product keeps hi*hi, hi*mid, mid*hi, mid*mid, hi*lo, lo*hi
+ *                (six BF16 MFMA products, about 2^-24 of |x||y| left out),
+ *                which reaches FP32-level accuracy on BF16 matrix cores.
+ *  For the reduced forms the omitted products (lo*lo; for BF16X3 mid*lo +
+ *  lo*mid + lo*lo) are added exactly (FP64) for the i = j pairs, where they
+ *  would otherwise bias C at zero displacement; off the diagonal they are
+ *  left out (rounding noise, <= 2^-16 (BF16), 2^-22 (FP16) or 2^-23 (BF16X3)
+ *  of |S_i||S_j| per term). */
 typedef enum {
     SDC_PREC_FP32 = 0,
     SDC_PREC_SPLIT_BF16 = 1,
-    SDC_PREC_SPLIT_FP16 = 2
+    SDC_PREC_SPLIT_FP16 = 2,
+    SDC_PREC_BF16X3 = 3
 } sdc_precision;
 
 /* Bin kinds.

@@ -188,7 +188,7 @@ sdc_status check_specs(const sdc_bin_spec* bins, const sdc_corr_spec* corr) {
     if (corr->n_lags < 1 || corr->n_lags > 1024) return set_err(SDC_ERR_INVALID_ARG, "n_lags must be in [1, 1024]");
     if (corr->origin_stride < 1 || corr->origin_stride > 64)
         return set_err(SDC_ERR_INVALID_ARG, "origin_stride must be in [1, 64]");
-    if (corr->precision < SDC_PREC_FP32 || corr->precision > SDC_PREC_SPLIT_FP16)
+    if (corr->precision < SDC_PREC_FP32 || corr->precision > SDC_PREC_BF16X3)
         return set_err(SDC_ERR_INVALID_ARG, "unknown precision");
     if ((corr->flags & ~SDC_FLAG_TIMING) != 0) return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
     if (bins->kind < SDC_BINS_PERIODIC_SC || bins->kind > SDC_BINS_RADIAL)
@@ -427,8 +427,9 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     // largest block read: 2(n_c - 1) + 1 (half) + u0_max / 8 + win_blocks - 1
     p->F8 = 2 * p->n_c + u0_max / 8 + sdc::win_blocks(lg) - 1;
     p->t_req = (int64_t)(corr->n_origins - 1) * sstr + corr->n_lags;
-    p->bytes_A = (size_t)3 * p->O8 * L.n_pad * 32;
-    p->bytes_B = (size_t)sstr * 3 * p->F8 * L.n_pad * 32;
+    const size_t elem = corr->precision == SDC_PREC_BF16X3 ? 48 : 32;  // bytes per pack element
+    p->bytes_A = (size_t)3 * p->O8 * L.n_pad * elem;
+    p->bytes_B = (size_t)sstr * 3 * p->F8 * L.n_pad * elem;
     if (sdc::fused_lds_bytes(L.win, corr->precision) > sdc::kMaxFusedLds) {
         delete p;
         return set_err(SDC_ERR_UNSUPPORTED, "histogram window does not fit in LDS");

@@ -16,10 +16,16 @@ namespace sdc {
 // spins, no counts).
 constexpr int kTile = 64;
 // Lags handled together by one fused task (consecutive lag indices u).
-// Split precisions take 8: a wave then holds 128 accumulator registers, two
+// The hi/lo splits take 8: a wave then holds 128 accumulator registers, two
 // workgroups fit on a CU and one workgroup's epilogue overlaps the other's
 // MFMA work.  FP32 takes 16 (one workgroup per CU): its MFMA is 16x slower
 // per flop, so operand reuse across more lags matters more than overlap.
+// The three-piece BF16 form (8 lags) has twice the split's MFMA work per
+// operand load and its operands take 1.5x the registers: it runs with one
+// workgroup per CU and a three-stage register prefetch, as FP32 does.
+constexpr bool one_wg_per_cu(int precision) {
+    return precision == SDC_PREC_FP32 || precision == SDC_PREC_BF16X3;
+}
 constexpr int lag_group(int precision) { return precision == SDC_PREC_FP32 ? 16 : 8; }
 // Pack elements (8 samples each) in one lane's B window: LG - 1 + 8 samples.
 constexpr int win_blocks(int lg) { return (lg + 14) / 8; }

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "sdc_internal.h"
@@ -29,6 +30,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 struct alignas(16) Chunk {
     uint4 x, y;
 };
+// 48-byte pack element of the three-piece BF16 form: 8 hi, 8 mid, 8 lo.
+struct alignas(16) Chunk3 {
+    uint4 x, y, z;
+};
+template <int PREC>
+using PackElem = typename std::conditional<PREC == SDC_PREC_BF16X3, Chunk3, Chunk>::type;
 
 // ---------------------------------------------------------------------------
 // pack
@@ -50,9 +57,23 @@ __device__ inline float f16_val(uint32_t bits) {
 }
 
 template <int PREC>
-__device__ inline Chunk make_chunk(const float v[8]) {
-    Chunk c;
-    if constexpr (PREC == SDC_PREC_FP32) {
+__device__ inline PackElem<PREC> make_chunk(const float v[8]) {
+    PackElem<PREC> c;
+    if constexpr (PREC == SDC_PREC_BF16X3) {
+        // x = hi + mid + lo exactly: each difference has at most 16 (then 8)
+        // significant bits and is exact in fp32
+        uint32_t hi[8], mi[8], lo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            hi[e] = bf16_bits(v[e]);
+            const float r1 = v[e] - bf16_val(hi[e]);
+            mi[e] = bf16_bits(r1);
+            lo[e] = bf16_bits(r1 - bf16_val(mi[e]));
+        }
+        c.x = make_uint4(hi[0] | hi[1] << 16, hi[2] | hi[3] << 16, hi[4] | hi[5] << 16, hi[6] | hi[7] << 16);
+        c.y = make_uint4(mi[0] | mi[1] << 16, mi[2] | mi[3] << 16, mi[4] | mi[5] << 16, mi[6] | mi[7] << 16);
+        c.z = make_uint4(lo[0] | lo[1] << 16, lo[2] | lo[3] << 16, lo[4] | lo[5] << 16, lo[6] | lo[7] << 16);
+    } else if constexpr (PREC == SDC_PREC_FP32) {
         c.x = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                          __float_as_uint(v[3]));
         c.y = make_uint4(__float_as_uint(v[4]), __float_as_uint(v[5]), __float_as_uint(v[6]),
@@ -109,15 +130,15 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
         v[1][e] = ok ? src[1] : 0.0f;
         v[2][e] = ok ? src[2] : 0.0f;
     }
-    Chunk* dst;
+    PackElem<PREC>* dst;
     int64_t comp_stride;
     if (isA) {
-        dst = (Chunk*)a.A + (int64_t)row * a.n_pad + p;
+        dst = (PackElem<PREC>*)a.A + (int64_t)row * a.n_pad + p;
         comp_stride = (int64_t)a.O8 * a.n_pad;
     } else {
         const int r = row - a.O8;
         const int ph = r / a.F8;
-        dst = (Chunk*)a.B + ((int64_t)ph * 3 * a.F8 + (r % a.F8)) * a.n_pad + p;
+        dst = (PackElem<PREC>*)a.B + ((int64_t)ph * 3 * a.F8 + (r % a.F8)) * a.n_pad + p;
         comp_stride = (int64_t)a.F8 * a.n_pad;
     }
 #pragma unroll
@@ -132,6 +153,7 @@ int launch_pack(const PackArgs& a, void* stream) {
         case SDC_PREC_FP32: hipLaunchKernelGGL(pack_kernel<SDC_PREC_FP32>, grid, block, 0, s, a); break;
         case SDC_PREC_SPLIT_BF16: hipLaunchKernelGGL(pack_kernel<SDC_PREC_SPLIT_BF16>, grid, block, 0, s, a); break;
         case SDC_PREC_SPLIT_FP16: hipLaunchKernelGGL(pack_kernel<SDC_PREC_SPLIT_FP16>, grid, block, 0, s, a); break;
+        case SDC_PREC_BF16X3: hipLaunchKernelGGL(pack_kernel<SDC_PREC_BF16X3>, grid, block, 0, s, a); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
@@ -172,7 +194,7 @@ __device__ inline uint4 slice8(const uint32_t (&w)[NW]) {
 
 template <int PREC>
 __device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
-    if constexpr (PREC == SDC_PREC_SPLIT_BF16) {
+    if constexpr (PREC == SDC_PREC_SPLIT_BF16 || PREC == SDC_PREC_BF16X3) {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
     } else {
@@ -190,6 +212,32 @@ __device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[NW],
     acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
     acc[M] = mfma16<PREC>(av.x, bl, acc[M]);
     acc[M] = mfma16<PREC>(av.y, bh, acc[M]);
+}
+
+// Three-piece BF16 for lag u0 + M: the six products hh, hm, mh, mm, hl, lh
+// (the dropped ml, lm, ll are below 2^-24 of the product).  The products of
+// order 2^-16 (mm, hl, lh) go to an accumulator of their own: added to the
+// large one they would fall below its last bit, where the matrix cores'
+// accumulation rounding is not unbiased.
+template <int M, int NW, int LG>
+__device__ inline void x3_step(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
+                               const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG]) {
+    const uint4 bh = slice8<M, NW>(wh);
+    const uint4 bm = slice8<M, NW>(wm);
+    const uint4 bl = slice8<M, NW>(wl);
+    acc[M] = mfma16<SDC_PREC_BF16X3>(av.x, bh, acc[M]);
+    acc[M] = mfma16<SDC_PREC_BF16X3>(av.x, bm, acc[M]);
+    acc[M] = mfma16<SDC_PREC_BF16X3>(av.y, bh, acc[M]);
+    acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.y, bm, acc_s[M]);
+    acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.x, bl, acc_s[M]);
+    acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.z, bh, acc_s[M]);
+}
+
+template <int NW, int LG, int... Ms>
+__device__ inline void x3_all(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
+                              const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG],
+                              std::integer_sequence<int, Ms...>) {
+    (x3_step<Ms, NW, LG>(av, wh, wm, wl, acc, acc_s), ...);
 }
 
 template <int PREC, int NW, int LG, int... Ms>
@@ -221,16 +269,40 @@ __device__ inline int pmod_dev(int a, int m) {
 
 // Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
 // B window of NB pack elements.
-template <int NB>
+// Accumulators of one wave: LG 32x32 tiles, and for the three-piece form a
+// second set for its small products.
+template <int PREC, int LG>
+struct Acc {
+    f32x16 v[LG];
+    f32x16 s[PREC == SDC_PREC_BF16X3 ? LG : 1];
+};
+
+template <int PREC, int NB>
 struct Stage {
-    Chunk a;
-    Chunk b[NB];
+    PackElem<PREC> a;
+    PackElem<PREC> b[NB];
 };
 
 template <int PREC, int NB, int LG>
-__device__ inline void stage_mma(const Stage<NB>& s, f32x16 (&acc)[LG]) {
+__device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, LG>& ac) {
+    f32x16 (&acc)[LG] = ac.v;
     constexpr int NW = 4 * NB;
-    if constexpr (PREC == SDC_PREC_FP32) {
+    if constexpr (PREC == SDC_PREC_BF16X3) {
+        uint32_t wh[NW], wm[NW], wl[NW];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const uint32_t h4[4] = {s.b[k].x.x, s.b[k].x.y, s.b[k].x.z, s.b[k].x.w};
+            const uint32_t m4[4] = {s.b[k].y.x, s.b[k].y.y, s.b[k].y.z, s.b[k].y.w};
+            const uint32_t l4[4] = {s.b[k].z.x, s.b[k].z.y, s.b[k].z.z, s.b[k].z.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                wh[4 * k + e] = h4[e];
+                wm[4 * k + e] = m4[e];
+                wl[4 * k + e] = l4[e];
+            }
+        }
+        x3_all<NW, LG>(s.a, wh, wm, wl, acc, ac.s, std::make_integer_sequence<int, LG>{});
+    } else if constexpr (PREC == SDC_PREC_FP32) {
         float af[8], w[8 * NB];
         const uint32_t ar[8] = {s.a.x.x, s.a.x.y, s.a.x.z, s.a.x.w, s.a.y.x, s.a.y.y, s.a.y.z, s.a.y.w};
 #pragma unroll
@@ -284,8 +356,9 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
     }
     __syncthreads();
 
-    const Chunk* Ab = (const Chunk*)a.A;
-    const Chunk* Bb = (const Chunk*)a.B + (int64_t)grp.phase * a.phase_stride;
+    using Elem = PackElem<PREC>;
+    const Elem* Ab = (const Elem*)a.A;
+    const Elem* Bb = (const Elem*)a.B + (int64_t)grp.phase * a.phase_stride;
     const int nk = 3 * a.n_c;
     const int ublk = grp.u0 / 8;
 
@@ -293,11 +366,17 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         const KPair pr = a.pairs[p];
         const int64_t si = (int64_t)pr.ti * kTile + wi * 32 + l32;
         const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
-        f32x16 acc[LG];
+        Acc<PREC, LG> acc;
 #pragma unroll
         for (int m = 0; m < LG; ++m)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[m][r] = 0.0f;
+            for (int r = 0; r < 16; ++r) acc.v[m][r] = 0.0f;
+        if constexpr (PREC == SDC_PREC_BF16X3) {
+#pragma unroll
+            for (int m = 0; m < LG; ++m)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc.s[m][r] = 0.0f;
+        }
 
         auto addrA = [&](int kk) {
             const int alpha = kk / a.n_c, c = kk - alpha * a.n_c;
@@ -309,18 +388,18 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         };
         // Register buffers: while K-step kk is multiplied the loads of later
         // steps are in flight (indices clamp to the last step).
-        auto load = [&](Stage<NB>& b, int kk) {
+        auto load = [&](Stage<PREC, NB>& b, int kk) {
             kk = kk < nk ? kk : nk - 1;
             b.a = *addrA(kk);
-            const Chunk* pb = addrB(kk);
+            const Elem* pb = addrB(kk);
 #pragma unroll
             for (int q = 0; q < NB; ++q) b.b[q] = pb[q * a.n_pad];
         };
-        if constexpr (PREC == SDC_PREC_FP32) {
+        if constexpr (one_wg_per_cu(PREC)) {
             // One wave per SIMD: three buffers keep two K-steps of loads in
             // flight.  nk = 3 * n_c is a multiple of 3, so the rotation needs
             // no tail; the scheduling barriers keep loads ahead of the MFMAs.
-            Stage<NB> s0, s1, s2;
+            Stage<PREC, NB> s0, s1, s2;
             load(s0, 0);
             load(s1, 1);
             for (int kk = 0; kk < nk; kk += 3) {
@@ -340,7 +419,7 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         } else {
             // Two waves per SIMD: two buffers; the other wave covers the rest
             // of the load latency.
-            Stage<NB> s0, s1;
+            Stage<PREC, NB> s0, s1;
             load(s0, 0);
             for (int kk = 0; kk < nk; kk += 2) {
                 load(s1, kk + 1);
@@ -378,7 +457,11 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         for (int m = 0; m < LG; ++m) {
             if ((grp.mask >> m) & 1) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) atomicAdd(&hist[m * a.win + bin[r]], (double)acc[m][r]);
+                for (int r = 0; r < 16; ++r) {
+                    double v = (double)acc.v[m][r];
+                    if constexpr (PREC == SDC_PREC_BF16X3) v += (double)acc.s[m][r];
+                    atomicAdd(&hist[m * a.win + bin[r]], v);
+                }
             }
         }
     }
@@ -410,7 +493,7 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
 }
 
 template <int PREC, int RADIAL>
-__global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_kernel(FusedArgs a) {
     extern __shared__ double hist[];
     // XCD-aware task order: consecutive tasks land on the same XCD (work-
     // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
@@ -432,7 +515,7 @@ __global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_kern
 // counter only grows and each queue is visited until it is found empty, so
 // every workgroup leaves the loop after at most total + 8 claims.
 template <int PREC, int RADIAL>
-__global__ __launch_bounds__(256, PREC == SDC_PREC_FP32 ? 1 : 2) void fused_batch_kernel(
+__global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_batch_kernel(
     const FusedArgs* __restrict__ args, const int64_t* __restrict__ task_start, int n_plans,
     unsigned* __restrict__ queue, int per, int total) {
     extern __shared__ double hist[];
@@ -504,6 +587,7 @@ int launch_fused(const FusedArgs& a, void* stream) {
         case SDC_PREC_FP32: return launch_fused_prec<SDC_PREC_FP32>(a, s);
         case SDC_PREC_SPLIT_BF16: return launch_fused_prec<SDC_PREC_SPLIT_BF16>(a, s);
         case SDC_PREC_SPLIT_FP16: return launch_fused_prec<SDC_PREC_SPLIT_FP16>(a, s);
+        case SDC_PREC_BF16X3: return launch_fused_prec<SDC_PREC_BF16X3>(a, s);
         default: return (int)hipErrorInvalidValue;
     }
 }
@@ -520,6 +604,7 @@ static const void* batch_kernel_of(int precision, int radial) {
             return radial ? batch_fn<SDC_PREC_SPLIT_BF16, 1>() : batch_fn<SDC_PREC_SPLIT_BF16, 0>();
         case SDC_PREC_SPLIT_FP16:
             return radial ? batch_fn<SDC_PREC_SPLIT_FP16, 1>() : batch_fn<SDC_PREC_SPLIT_FP16, 0>();
+        case SDC_PREC_BF16X3: return radial ? batch_fn<SDC_PREC_BF16X3, 1>() : batch_fn<SDC_PREC_BF16X3, 0>();
         default: return nullptr;
     }
 }
@@ -561,6 +646,10 @@ int launch_fused_batch(const BatchLaunch& b, void* stream) {
         case SDC_PREC_SPLIT_FP16:
             if (b.radial) SDC_BATCH(SDC_PREC_SPLIT_FP16, 1);
             else SDC_BATCH(SDC_PREC_SPLIT_FP16, 0);
+            break;
+        case SDC_PREC_BF16X3:
+            if (b.radial) SDC_BATCH(SDC_PREC_BF16X3, 1);
+            else SDC_BATCH(SDC_PREC_BF16X3, 0);
             break;
         default: return (int)hipErrorInvalidValue;
     }
@@ -650,6 +739,22 @@ __device__ inline double split_lo(float v) {
     else return 0.0;
 }
 
+// The part of x*y that the reduced-precision contraction leaves out, from
+// the pieces the pack kernel forms (FP64, exact): lo*lo for the hi/lo splits;
+// mid*lo + lo*mid + lo*lo for the three-piece form.
+template <int PREC>
+__device__ inline double dropped_product(float x, float y) {
+    if constexpr (PREC == SDC_PREC_BF16X3) {
+        const float rx = x - bf16_val(bf16_bits(x)), ry = y - bf16_val(bf16_bits(y));
+        const double mx = (double)bf16_val(bf16_bits(rx)), my = (double)bf16_val(bf16_bits(ry));
+        const double lx = (double)bf16_val(bf16_bits(rx - (float)mx));
+        const double ly = (double)bf16_val(bf16_bits(ry - (float)my));
+        return mx * ly + lx * my + lx * ly;
+    } else {
+        return split_lo<PREC>(x) * split_lo<PREC>(y);
+    }
+}
+
 // Block: up to 16 consecutive sites.  With USE_LDS their whole time series
 // sits in LDS; otherwise the samples are read from global memory.
 // Thread (site q = tid / 16, lane r = tid % 16) takes lags r, r + 16, ...
@@ -697,7 +802,7 @@ __global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_blo
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     s += (double)x0[c] * (double)x1[c];
-                    if constexpr (PREC != SDC_PREC_FP32) sl += split_lo<PREC>(x0[c]) * split_lo<PREC>(x1[c]);
+                    if constexpr (PREC != SDC_PREC_FP32) sl += dropped_product<PREC>(x0[c], x1[c]);
                 }
             }
             atomicAdd(&part[l], s);
@@ -723,6 +828,9 @@ static void launch_self_kind(const SelfArgs& a, dim3 grid, int lds, hipStream_t 
             break;
         case SDC_PREC_SPLIT_FP16:
             hipLaunchKernelGGL((self_kernel<USE_LDS, SDC_PREC_SPLIT_FP16>), grid, dim3(256), lds, s, a, spb);
+            break;
+        case SDC_PREC_BF16X3:
+            hipLaunchKernelGGL((self_kernel<USE_LDS, SDC_PREC_BF16X3>), grid, dim3(256), lds, s, a, spb);
             break;
         default:
             hipLaunchKernelGGL((self_kernel<USE_LDS, SDC_PREC_FP32>), grid, dim3(256), lds, s, a, spb);
@@ -798,16 +906,19 @@ int prepare_kernels() {
         (const void*)fused_kernel<SDC_PREC_FP32, 0>,        (const void*)fused_kernel<SDC_PREC_FP32, 1>,
         (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0>,  (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1>,
         (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0>,  (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1>,
+        (const void*)fused_kernel<SDC_PREC_BF16X3, 0>,      (const void*)fused_kernel<SDC_PREC_BF16X3, 1>,
         batch_fn<SDC_PREC_FP32, 0>(),                       batch_fn<SDC_PREC_FP32, 1>(),
         batch_fn<SDC_PREC_SPLIT_BF16, 0>(),                 batch_fn<SDC_PREC_SPLIT_BF16, 1>(),
-        batch_fn<SDC_PREC_SPLIT_FP16, 0>(),                 batch_fn<SDC_PREC_SPLIT_FP16, 1>()};
+        batch_fn<SDC_PREC_SPLIT_FP16, 0>(),                 batch_fn<SDC_PREC_SPLIT_FP16, 1>(),
+        batch_fn<SDC_PREC_BF16X3, 0>(),                     batch_fn<SDC_PREC_BF16X3, 1>()};
     for (const void* f : fused) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxFusedLds);
         if (e != hipSuccess) return (int)e;
     }
     const void* self[] = {(const void*)self_kernel<true, SDC_PREC_FP32>,
                           (const void*)self_kernel<true, SDC_PREC_SPLIT_BF16>,
-                          (const void*)self_kernel<true, SDC_PREC_SPLIT_FP16>};
+                          (const void*)self_kernel<true, SDC_PREC_SPLIT_FP16>,
+                          (const void*)self_kernel<true, SDC_PREC_BF16X3>};
     for (const void* f : self) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSelfLdsBudget);
         if (e != hipSuccess) return (int)e;

@@ -17,12 +17,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsdc.so")
 
 OK, ERR_INVALID_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED, ERR_NO_DEVICE = range(7)
-PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16 = 0, 1, 2
+PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PREC_BF16X3 = 0, 1, 2, 3
 BINS_SC, BINS_BCC, BINS_RADIAL = 0, 1, 2
 COUPLING_NN_UNIFORM, COUPLING_NN_RANDOM_SIGN, COUPLING_EXP_CUTOFF = 0, 1, 2
 INIT_UNIFORM, INIT_PERTURBED_Z, INIT_GIVEN = 0, 1, 2
 
-PRECISIONS = {"fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16, "split_fp16": PREC_SPLIT_FP16}
+PRECISIONS = {"fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16, "split_fp16": PREC_SPLIT_FP16,
+              "bf16x3": PREC_BF16X3}
 
 
 class SdcError(RuntimeError):

@@ -17,7 +17,7 @@ from paper_2308_07487_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL_RANDOM = {"fp32": 1e-6, "split_bf16": 1e-6, "split_fp16": 1e-6}
+TOL_RANDOM = {"fp32": 1e-6, "split_bf16": 1e-6, "split_fp16": 1e-6, "bf16x3": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -77,7 +77,7 @@ def _plans_and_frames(torch, S, prec, samples, dyadic=False):
     return plans, frames, host
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "bf16x3"])
 def test_batch_matches_oracle(torch_dev, S, orc, prec):
     _say(f"batch of {len(SAMPLES)} mixed samples, {prec}")
     plans, frames, host = _plans_and_frames(torch_dev, S, prec, SAMPLES)

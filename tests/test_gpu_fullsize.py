@@ -87,11 +87,12 @@ def _periodic_case(torch, S, orc, L, J, init, sigma, seed, n_o, n_L, prec, bar, 
     assert e <= bar and ident <= max(bar, _sum_bar(prec, n_o))
 
 
-@pytest.mark.parametrize("prec,bar", [("split_fp16", 1e-6), ("split_bf16", 5e-5)])
+@pytest.mark.parametrize("prec,bar", [("split_fp16", 1e-6), ("split_bf16", 5e-5), ("bf16x3", 1e-6)])
 def test_sc32_fm_full(torch_dev, S, orc, prec, bar):
     """sc 32^3 ferromagnet from a z-aligned start (sigma = 0.3): spins stay
     nearly parallel, so split-BF16's rounding is coherent and only its
-    deterministic bound applies; split-FP16 meets 1e-6."""
+    deterministic bound applies; split-FP16 and the three-piece BF16 form
+    meet 1e-6."""
     _say(f"sc 32^3 FM full size {prec}")
     _periodic_case(torch_dev, S, orc, (32, 32, 32), -1.0, S.INIT_PERTURBED_Z, 0.3, 0x5DC00001, 64, 256,
                    prec, bar, 5)

@@ -99,12 +99,20 @@ typedef struct {
     int32_t origin_stride; /* frames between origins s, >= 1 (origin o uses  */
                            /* frame o*s; lag t pairs it with frame o*s + t)  */
     int32_t precision;     /* sdc_precision                                  */
-    int32_t flags;         /* 0 or SDC_FLAG_TIMING                           */
+    int32_t flags;         /* SDC_FLAG_TIMING | SDC_FLAG_CONNECTED           */
 } sdc_corr_spec;
 
 /* flags: record HIP events around each kernel of sdc_accumulate (on the
  * caller's stream) so sdc_plan_timings can report per-kernel durations. */
 #define SDC_FLAG_TIMING 1
+/* flags: connected correlation, Eq. (4) with its second term: every
+ * accumulate subtracts the product of the per-site averages over its own
+ * origins, H[t][b] += sum_o (S_i(o s) - <S_i>).S_j(o s + t) with
+ * <S_i> = (1/n_origins) sum_o S_i(o s) -- the covariance form of Eq. (5),
+ * which needs the centring on the origin side only (the centred values sum
+ * to zero over the origins).  The self term and the site sum (C_sum) are
+ * connected the same way. */
+#define SDC_FLAG_CONNECTED 2
 
 typedef struct sdc_plan sdc_plan;
 

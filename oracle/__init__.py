@@ -10,7 +10,10 @@ Each function states the paper passage it follows (arXiv 2308.07487):
 
 - ``binned_corr``      Eq. (4) unsubtracted, summed over alpha as in Eq. (3),
                        cast per lag as the GEMM of Sec. 3.2 and binned by a
-                       key computed from positions (the role of Q in Eq. (6)).
+                       key computed from positions (the role of Q in Eq. (6));
+                       with ``connected=True`` the second term of Eq. (4), the
+                       product of the per-site averages over the origins
+                       (``mean_product``), is subtracted.
 - ``finalize``         per-bin normalisation, site sum (Sec. 1: summing the
                        correlation over all sites) and the windowed time
                        transform of Sec. 2.2.
@@ -66,6 +69,9 @@ def lib():
         L.oracle_binned_corr_select.argtypes = [P, i64, ctypes.c_int, P, i32, f32, P, i64, i32,
                                                 i32, P, i32, P, i32, P, P, ctypes.c_int]
         L.oracle_self_corr.argtypes = [P, i64, i64, i32, i32, P, i32, P]
+        L.oracle_mean_product.argtypes = [P, i64, ctypes.c_int, P, i32, f32, P, i64, i32, i32,
+                                          P, i32, i64, i64, P, i32, P, ctypes.c_int]
+        L.oracle_self_mean_product.argtypes = [P, i64, i64, i32, i32, P, i32, P]
         L.oracle_dft.argtypes = [P, i32, P]
         L.oracle_finalize.argtypes = [P, P, i64, i32, i64, P, P, P, P, P, P, P]
         L.oracle_ll_rk4.argtypes = [i64, P, P, P, P, f64, i64, P]
@@ -75,7 +81,7 @@ def lib():
         for name in ("oracle_n_bins", "oracle_pair_keys", "oracle_binned_corr",
                      "oracle_binned_corr_select", "oracle_self_corr", "oracle_dft",
                      "oracle_finalize", "oracle_ll_rk4", "oracle_philox", "oracle_init_state",
-                     "oracle_philox_block"):
+                     "oracle_philox_block", "oracle_mean_product", "oracle_self_mean_product"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -117,12 +123,13 @@ def pair_keys(pos, kind, pi, pj, cells=None, n_shells=0, r_max=0.0):
 
 
 def binned_corr(pos, frames, kind, n_origins, lags, stride=1, cells=None, n_shells=0,
-                r_max=0.0, rows=None, counts=True, n_threads=0):
+                r_max=0.0, rows=None, counts=True, n_threads=0, connected=False):
     """Raw binned sums H[l][b] (FP64) and pair counts (uint64).
 
     H[l][b] = sum over ordered pairs (i, j) with key(i, j) = b of
               sum_{o < n_origins} S_i(o*stride) . S_j(o*stride + lags[l]).
     ``rows`` = (i_begin, i_end) restricts the origin sites (partial sums).
+    ``connected``: subtract ``mean_product`` (Eq. (4), second term).
     """
     pos = np.ascontiguousarray(pos, dtype=np.float32)
     frames = np.ascontiguousarray(frames, dtype=np.float32)
@@ -138,11 +145,39 @@ def binned_corr(pos, frames, kind, n_origins, lags, stride=1, cells=None, n_shel
                                     frames.shape[0], int(n_origins), int(stride), _ptr(lags),
                                     lags.shape[0], int(i0), int(i1), _ptr(H), _ptr(C),
                                     int(n_threads)), "binned_corr")
+    if connected:
+        H -= mean_product(pos, frames, kind, n_origins, lags, stride=stride, cells=cells,
+                          n_shells=n_shells, r_max=r_max, rows=rows, n_threads=n_threads)
     return H, C
 
 
+def mean_product(pos, frames, kind, n_origins, lags, stride=1, cells=None, n_shells=0,
+                 r_max=0.0, rows=None, bins=None, n_threads=0):
+    """Second term of Eq. (4), binned like ``binned_corr``:
+    P[l][b] = n_origins * sum over ordered pairs (i, j) with key(i, j) = b of
+              <S_i(t0)> . <S_j(t0 + lags[l])>, <.> = average over t0 = o*stride.
+    ``bins``: only these bins (P is then [n_lags][len(bins)])."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    frames = np.ascontiguousarray(frames, dtype=np.float32)
+    n = pos.shape[0]
+    kind_, cells_, ns, rm = _spec(kind, cells, n_shells, r_max)
+    lags = np.ascontiguousarray(lags, dtype=np.int32)
+    i0, i1 = (0, n) if rows is None else rows
+    if bins is None:
+        width, bp, nsel = n_bins(pos, kind, cells, n_shells, r_max), None, 0
+    else:
+        bins = np.ascontiguousarray(bins, dtype=np.int64)
+        width, bp, nsel = bins.shape[0], _ptr(bins), bins.shape[0]
+    P = np.zeros((lags.shape[0], width), dtype=np.float64)
+    _check(lib().oracle_mean_product(_ptr(pos), n, kind_, _ptr(cells_), ns, rm, _ptr(frames),
+                                     frames.shape[0], int(n_origins), int(stride), _ptr(lags),
+                                     lags.shape[0], int(i0), int(i1), bp, int(nsel), _ptr(P),
+                                     int(n_threads)), "mean_product")
+    return P
+
+
 def binned_corr_select(pos, frames, kind, n_origins, lags, bins, stride=1, cells=None,
-                       n_shells=0, r_max=0.0, n_threads=0):
+                       n_shells=0, r_max=0.0, n_threads=0, connected=False):
     """H restricted to selected bins: returns (H_sel[n_lags][n_sel], counts_sel)."""
     pos = np.ascontiguousarray(pos, dtype=np.float32)
     frames = np.ascontiguousarray(frames, dtype=np.float32)
@@ -156,16 +191,26 @@ def binned_corr_select(pos, frames, kind, n_origins, lags, bins, stride=1, cells
                                            int(stride), _ptr(lags), lags.shape[0], _ptr(bins),
                                            bins.shape[0], _ptr(H), _ptr(C), int(n_threads)),
            "binned_corr_select")
+    if connected:
+        H -= mean_product(pos, frames, kind, n_origins, lags, stride=stride, cells=cells,
+                          n_shells=n_shells, r_max=r_max, bins=bins, n_threads=n_threads)
     return H, C
 
 
-def self_corr(frames, n_origins, lags, stride=1):
-    """sum_o sum_i S_i(o*stride) . S_i(o*stride + lag), per lag (FP64)."""
+def self_corr(frames, n_origins, lags, stride=1, connected=False):
+    """sum_o sum_i S_i(o*stride) . S_i(o*stride + lag), per lag (FP64); with
+    ``connected`` minus n_origins * sum_i <S_i(t0)> . <S_i(t0 + lag)>."""
     frames = np.ascontiguousarray(frames, dtype=np.float32)
     lags = np.ascontiguousarray(lags, dtype=np.int32)
     out = np.zeros(lags.shape[0], dtype=np.float64)
     _check(lib().oracle_self_corr(_ptr(frames), frames.shape[1], frames.shape[0], int(n_origins),
                                   int(stride), _ptr(lags), lags.shape[0], _ptr(out)), "self_corr")
+    if connected:
+        mp = np.zeros(lags.shape[0], dtype=np.float64)
+        _check(lib().oracle_self_mean_product(_ptr(frames), frames.shape[1], frames.shape[0],
+                                              int(n_origins), int(stride), _ptr(lags), lags.shape[0],
+                                              _ptr(mp)), "self_mean_product")
+        out -= mp
     return out
 
 

@@ -11,7 +11,9 @@
  * Simulations on Nvidia GPUs using Tensor Core", arXiv 2308.07487):
  *
  *  - the pair correlation of Eq. (4), in its unsubtracted form
- *    <S_i(t0) . S_j(t0 + t)>, summed over the three components alpha as in
+ *    <S_i(t0) . S_j(t0 + t)> and, as its second term, the product of the
+ *    per-site averages <S_i(t0)> . <S_j(t0 + t)> that the connected form
+ *    subtracts, summed over the three components alpha as in
  *    Eq. (3), averaged over time origins t0 = o*s (o = 0..n_o-1) instead of
  *    Monte Carlo realizations, and binned by the displacement of site j (the
  *    later time) relative to site i (the origin);
@@ -369,6 +371,118 @@ int oracle_binned_corr_select(const float *pos, int64_t n, int kind,
             for (int32_t s = 0; s < n_sel; ++s) counts_sel[s] += pc[(size_t)t * n_sel + s];
     }
     free(priv); free(pc); free(slot); okeys_free(&k);
+    return OR_OK;
+}
+
+/* Per-site averages over the origins, Eq. (4): out[i] = (1/n_o) sum_o
+ * S_i(o*s + shift), FP64, [n][3]. */
+static void omean(const float *frames, int64_t n, int32_t n_origins, int32_t stride,
+                  int32_t shift, double *out) {
+    for (int64_t i = 0; i < n; ++i) {
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int32_t o = 0; o < n_origins; ++o) {
+            const float *x = frames + (((int64_t)o * stride + shift) * n + i) * 3;
+            a[0] += (double)x[0];
+            a[1] += (double)x[1];
+            a[2] += (double)x[2];
+        }
+        for (int c = 0; c < 3; ++c) out[3 * i + c] = a[c] / (double)n_origins;
+    }
+}
+
+/*
+ * Second term of Eq. (4), binned like H: P[l][b] += n_o * sum over ordered
+ * pairs (i, j), i in [i_begin, i_end), key(i, j) = b, of
+ *     <S_i(t0)> . <S_j(t0 + lags[l])>,
+ * where <.> averages over the origins t0 = o*s, o < n_o.  With bins != NULL
+ * only the n_sel listed bins are accumulated (P: [n_lags][n_sel]); otherwise
+ * P is [n_lags][n_bins].  The connected correlation is H - P.
+ */
+int oracle_mean_product(const float *pos, int64_t n, int kind, const int32_t *L,
+                        int32_t n_shells, float r_max, const float *frames,
+                        int64_t n_frames, int32_t n_origins, int32_t stride,
+                        const int32_t *lags, int32_t n_lags, int64_t i_begin,
+                        int64_t i_end, const int64_t *bins, int32_t n_sel,
+                        double *P, int n_threads) {
+    okeys k;
+    int rc = okeys_init(&k, pos, n, kind, L, n_shells, r_max);
+    if (rc != OR_OK) { okeys_free(&k); return rc; }
+    rc = check_frames(n_frames, n_origins, stride, lags, n_lags);
+    if (rc != OR_OK || i_begin < 0 || i_end > n || i_begin > i_end || (bins && n_sel < 0)) {
+        okeys_free(&k);
+        return OR_EINVAL;
+    }
+    const int64_t width = bins ? n_sel : k.n_bins;
+    int32_t *slot = (int32_t *)malloc(sizeof(int32_t) * (size_t)k.n_bins);
+    double *m0 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *mt = (double *)malloc(sizeof(double) * 3 * (size_t)n * (size_t)(n_lags > 0 ? n_lags : 1));
+    if (!slot || !m0 || !mt) { free(slot); free(m0); free(mt); okeys_free(&k); return OR_ENOMEM; }
+    for (int64_t b = 0; b < k.n_bins; ++b) slot[b] = bins ? -1 : (int32_t)b;
+    if (bins) {
+        for (int32_t q = 0; q < n_sel; ++q) {
+            if (bins[q] < 0 || bins[q] >= k.n_bins || slot[bins[q]] >= 0) {
+                free(slot); free(m0); free(mt); okeys_free(&k);
+                return OR_EINVAL;
+            }
+            slot[bins[q]] = q;
+        }
+    }
+    omean(frames, n, n_origins, stride, 0, m0);
+    for (int32_t l = 0; l < n_lags; ++l) omean(frames, n, n_origins, stride, lags[l], mt + (size_t)l * 3 * n);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+    double *priv = (double *)calloc((size_t)nt * n_lags * (size_t)(width > 0 ? width : 1), sizeof(double));
+    if (!priv) { free(slot); free(m0); free(mt); okeys_free(&k); return OR_ENOMEM; }
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *h = priv + (size_t)tid * n_lags * width;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t i = i_begin; i < i_end; ++i) {
+            for (int64_t j = 0; j < n; ++j) {
+                const int32_t q = slot[okey(&k, i, j)];
+                if (q < 0) continue;
+                for (int32_t l = 0; l < n_lags; ++l) {
+                    const double *a = m0 + 3 * i;
+                    const double *b = mt + ((size_t)l * n + j) * 3;
+                    h[(size_t)l * width + q] += (double)n_origins * (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+                }
+            }
+        }
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int64_t x = 0; x < (int64_t)n_lags * width; ++x) P[x] += priv[(size_t)t * n_lags * width + x];
+    free(priv); free(slot); free(m0); free(mt); okeys_free(&k);
+    return OR_OK;
+}
+
+/* Self part of the second term of Eq. (4):
+ * out[l] += n_o * sum_i <S_i(t0)> . <S_i(t0 + lags[l])>. */
+int oracle_self_mean_product(const float *frames, int64_t n, int64_t n_frames,
+                             int32_t n_origins, int32_t stride, const int32_t *lags,
+                             int32_t n_lags, double *out) {
+    int rc = check_frames(n_frames, n_origins, stride, lags, n_lags);
+    if (rc != OR_OK || n <= 0) return OR_EINVAL;
+    double *m0 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *mt = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!m0 || !mt) { free(m0); free(mt); return OR_ENOMEM; }
+    omean(frames, n, n_origins, stride, 0, m0);
+    for (int32_t l = 0; l < n_lags; ++l) {
+        omean(frames, n, n_origins, stride, lags[l], mt);
+        double s = 0.0;
+        for (int64_t i = 0; i < 3 * n; ++i) s += m0[i] * mt[i];
+        out[l] += (double)n_origins * s;
+    }
+    free(m0); free(mt);
     return OR_OK;
 }
 

@@ -119,6 +119,7 @@ struct sdc_plan {
     double* d_norg = nullptr;
     double* d_msum = nullptr;    // [n_lags] sum_o M . M (site-summed raw correlation)
     double* d_mframe = nullptr;  // [t_req][3] per-frame site sums (scratch)
+    float* d_mean = nullptr;     // [n][4] origin averages (connected form, scratch)
     double* d_C = nullptr;
     double* d_fin = nullptr;  // csum, cself, ssum[2], sself[2]
     void* d_A = nullptr;
@@ -190,7 +191,8 @@ sdc_status check_specs(const sdc_bin_spec* bins, const sdc_corr_spec* corr) {
         return set_err(SDC_ERR_INVALID_ARG, "origin_stride must be in [1, 64]");
     if (corr->precision < SDC_PREC_FP32 || corr->precision > SDC_PREC_BF16X3)
         return set_err(SDC_ERR_INVALID_ARG, "unknown precision");
-    if ((corr->flags & ~SDC_FLAG_TIMING) != 0) return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
+    if ((corr->flags & ~(SDC_FLAG_TIMING | SDC_FLAG_CONNECTED)) != 0)
+        return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
     if (bins->kind < SDC_BINS_PERIODIC_SC || bins->kind > SDC_BINS_RADIAL)
         return set_err(SDC_ERR_INVALID_ARG, "unknown bin kind");
     return SDC_OK;
@@ -265,8 +267,12 @@ sdc_status queue_pack_self(sdc_plan* p, const LagSel& sel, const float* spins_de
     pa.frames_valid = std::min<int64_t>(n_frames, p->t_req);
     pa.A = p->d_A;
     pa.B = p->d_B;
+    pa.mean = p->d_mean;
     if (timing) SDC_HIP(hipEventRecord(p->ev[0], hs), "hipEventRecord");
-    int e = sdc::launch_pack(pa, stream);
+    int e = 0;
+    if (p->d_mean)
+        e = sdc::launch_mean(spins_dev, L.n, p->corr.n_origins, p->corr.origin_stride, p->d_mean, stream);
+    if (e == 0) e = sdc::launch_pack(pa, stream);
     if (e != 0) {
         p->failed = true;
         return hip_err(e, "pack kernel");
@@ -287,6 +293,7 @@ sdc_status queue_pack_self(sdc_plan* p, const LagSel& sel, const float* spins_de
     sa.norg = p->d_norg;
     sa.mframe = p->d_mframe;
     sa.msum = p->d_msum;
+    sa.mean = p->d_mean;
     if (timing) SDC_HIP(hipEventRecord(p->ev[1], hs), "hipEventRecord");
     e = sdc::launch_self(sa, stream);
     if (e != 0) {
@@ -471,6 +478,7 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     TRY(dalloc(&p->d_norg, (size_t)corr->n_lags, &p->owned));
     TRY(dalloc(&p->d_msum, (size_t)corr->n_lags, &p->owned));
     TRY(dalloc(&p->d_mframe, (size_t)p->t_req * 3, &p->owned));
+    if (corr->flags & SDC_FLAG_CONNECTED) TRY(dalloc(&p->d_mean, (size_t)L.n * 4, &p->owned));
     TRY(dalloc(&p->d_fin, (size_t)6 * corr->n_lags, &p->owned));
     TRY(dalloc((char**)&p->d_A, p->bytes_A, &p->owned));
     TRY(dalloc((char**)&p->d_B, p->bytes_B, &p->owned));

@@ -146,6 +146,7 @@ struct PackArgs {
     int F8;               // frame blocks of 8 in each B phase pack
     int n_phase;          // = stride
     int64_t frames_valid; // frames usable: min(n_frames, required)
+    const float* mean;    // [n][4] per-site origin averages subtracted from A, or null
     void* A;              // [3][O8][n_pad] x 32 B
     void* B;              // [n_phase][3][F8][n_pad] x 32 B
 };
@@ -221,8 +222,12 @@ struct SelfArgs {
     double* norg;         // [n_lags] origin totals, += n_origins per selected lag
     double* mframe;       // [t_need][3] scratch: site-summed spin of each frame
     double* msum;         // [n_lags] += sum_o M(o s) . M(o s + t)
+    const float* mean;    // [n][4] origin averages (connected form), or null
 };
 int launch_self(const SelfArgs& a, void* stream);
+// Per-site averages over the origins of one accumulate (connected form):
+// mean[4 i + c] = fp32((1/n_o) sum_o S_i^c(o s)), summed in FP64.
+int launch_mean(const float* frames, int64_t n, int n_origins, int stride, float* mean, void* stream);
 
 struct FinalArgs {
     const double* H;

@@ -129,6 +129,14 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
         v[0][e] = ok ? src[0] : 0.0f;
         v[1][e] = ok ? src[1] : 0.0f;
         v[2][e] = ok ? src[2] : 0.0f;
+        // connected form: the origin side is centred on its average over the
+        // origins (Eq. (5)); since the centred values sum to zero over the
+        // origins, the later side needs no centring
+        if (isA && ok && a.mean) {
+            v[0][e] -= a.mean[4 * orig];
+            v[1][e] -= a.mean[4 * orig + 1];
+            v[2][e] -= a.mean[4 * orig + 2];
+        }
     }
     PackElem<PREC>* dst;
     int64_t comp_stride;
@@ -784,6 +792,9 @@ __global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_blo
     }
     __syncthreads();
     const int q = tid / 16, r = tid % 16;
+    float mu[3] = {0.0f, 0.0f, 0.0f};  // origin-side average (connected form)
+    if (a.mean && q < nsb)
+        for (int c = 0; c < 3; ++c) mu[c] = a.mean[4 * (i0 + q) + c];
     if (q < nsb) {
         for (int l = r; l < a.n_sel; l += 16) {
             const int t = a.lags[l];
@@ -801,8 +812,9 @@ __global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_blo
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    s += (double)x0[c] * (double)x1[c];
-                    if constexpr (PREC != SDC_PREC_FP32) sl += dropped_product<PREC>(x0[c], x1[c]);
+                    const float u = x0[c] - mu[c];  // as the pack kernel forms it
+                    s += (double)u * (double)x1[c];
+                    if constexpr (PREC != SDC_PREC_FP32) sl += dropped_product<PREC>(u, x1[c]);
                 }
             }
             atomicAdd(&part[l], s);
@@ -866,17 +878,49 @@ __global__ __launch_bounds__(256) void magnet_kernel(const float* __restrict__ f
 // Site-summed correlation of each selected lag: the sum over all ordered
 // pairs of S_i(o s) . S_j(o s + t) equals M(o s) . M(o s + t), summed over
 // the origins in FP64 (one thread per lag).
+// For the connected form the origin side is centred: the sum over all pairs
+// of (S_i(o s) - <S_i>) . S_j(o s + t) is (M(o s) - <M>) . M(o s + t).
 __global__ __launch_bounds__(256) void msum_kernel(SelfArgs a) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= a.n_sel) return;
     const int t = a.lags[l];
+    double mb[3] = {0.0, 0.0, 0.0};
+    if (a.mean) {
+        for (int o = 0; o < a.n_origins; ++o)
+            for (int c = 0; c < 3; ++c) mb[c] += a.mframe[(int64_t)o * a.stride * 3 + c];
+        for (int c = 0; c < 3; ++c) mb[c] /= (double)a.n_origins;
+    }
     double s = 0.0;
     for (int o = 0; o < a.n_origins; ++o) {
         const double* m0 = a.mframe + (int64_t)o * a.stride * 3;
         const double* m1 = m0 + (int64_t)t * 3;
-        s += m0[0] * m1[0] + m0[1] * m1[1] + m0[2] * m1[2];
+        s += (m0[0] - mb[0]) * m1[0] + (m0[1] - mb[1]) * m1[1] + (m0[2] - mb[2]) * m1[2];
     }
     a.msum[t] += s;
+}
+
+__global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ frames, int64_t n, int n_origins,
+                                                   int stride, float* __restrict__ mean) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int o = 0; o < n_origins; ++o) {
+        const float* x = frames + ((int64_t)o * stride * n + i) * 3;
+        s0 += (double)x[0];
+        s1 += (double)x[1];
+        s2 += (double)x[2];
+    }
+    const double inv = 1.0 / (double)n_origins;
+    mean[4 * i] = (float)(s0 * inv);
+    mean[4 * i + 1] = (float)(s1 * inv);
+    mean[4 * i + 2] = (float)(s2 * inv);
+    mean[4 * i + 3] = 0.0f;
+}
+
+int launch_mean(const float* frames, int64_t n, int n_origins, int stride, float* mean, void* stream) {
+    hipLaunchKernelGGL(mean_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       frames, n, n_origins, stride, mean);
+    return (int)hipGetLastError();
 }
 
 int launch_self(const SelfArgs& a, void* stream) {

@@ -253,3 +253,60 @@ def test_invalid_calls(torch_dev, S):
         # the plan stays usable after rejected calls
         p.accumulate(torch_dev.zeros((40, 64, 3), device="cuda"))
         p.finalize()
+
+
+CONNECTED_CASES = [
+    ("sc 5x4x6", "sc", (5, 4, 6), {}),
+    ("bcc 3x4x3", "bcc", (3, 4, 3), {}),
+    ("radial 400 points, 64 shells", "radial", None, dict(n_shells=64, r_max=8.0)),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "split_fp16", "bf16x3"])
+@pytest.mark.parametrize("case", CONNECTED_CASES, ids=[c[0] for c in CONNECTED_CASES])
+def test_connected_matches_oracle(torch_dev, S, orc, case, prec):
+    """Connected form (Eq. (4) with its second term): the GPU centres the
+    origin side (Eq. (5)); the oracle subtracts the product of the averages."""
+    name, lat, L, spec = case
+    _say(f"connected {name} {prec}")
+    if lat == "sc":
+        pos, kind, okind, kw = inputs.sc_positions(L), S.BINS_SC, orc.SC, dict(cells=L)
+    elif lat == "bcc":
+        pos, kind, okind, kw = inputs.bcc_positions(L), S.BINS_BCC, orc.BCC, dict(cells=L)
+    else:
+        pos, kind, okind, kw = inputs.ball_positions(400, 4.0, 3), S.BINS_RADIAL, orc.RADIAL, spec
+    n = pos.shape[0]
+    n_o, n_L, s = 21, 19, 2
+    fr = inputs.random_unit_frames((n_o - 1) * s + n_L, n, seed=31).astype(np.float64)
+    fr[:, :, 2] += 0.4  # a non-zero average that the connected form removes
+    fr = fr.astype(np.float32)
+    with S.Plan(pos, kind, n_o, n_L, prec, origin_stride=s, connected=True, **kw) as p:
+        p.accumulate(torch_dev.from_numpy(fr).cuda())
+        out = p.finalize()
+    lags = np.arange(n_L)
+    Hr, cr = orc.binned_corr(pos, fr, okind, n_o, lags, stride=s, connected=True, **kw)
+    sfr = orc.self_corr(fr, n_o, lags, stride=s, connected=True)
+    np.testing.assert_array_equal(out["counts"], cr)
+    C, Cs, Cf, Ss, Sf = orc.finalize(Hr, cr, n, float(n_o), sfr)
+    e = _normwise(out["C"], C)
+    print(f"  normwise error {e:.3e}", flush=True)
+    assert e <= max(_tol_random(prec, cr, n_o), TOL[prec] if prec == "split_bf16" else 0.0)
+    # the origin side is centred in fp32, as the packed operand is
+    np.testing.assert_allclose(out["Cself"], Cf, rtol=1e-7, atol=1e-7)
+    assert _normwise(out["Csum"], Cs) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16", "bf16x3"])
+def test_connected_static_is_zero(torch_dev, S, prec):
+    """Spins constant in time: the origin side equals its average, so the
+    connected correlation vanishes identically."""
+    _say(f"connected static {prec}")
+    L = (4, 4, 5)
+    pos = inputs.sc_positions(L)
+    fr = inputs.static_frames(30, pos.shape[0], (0.3, -0.55, 0.7))
+    with S.Plan(pos, S.BINS_SC, 16, 15, prec, cells=L, connected=True) as p:
+        p.accumulate(torch_dev.from_numpy(fr).cuda())
+        out = p.finalize()
+    assert np.max(np.abs(out["C"])) == 0.0
+    assert np.max(np.abs(out["Cself"])) == 0.0
+    assert np.max(np.abs(out["Csum"])) < 1e-12

@@ -99,7 +99,8 @@ typedef struct {
     int32_t origin_stride; /* frames between origins s, >= 1 (origin o uses  */
                            /* frame o*s; lag t pairs it with frame o*s + t)  */
     int32_t precision;     /* sdc_precision                                  */
-    int32_t flags;         /* SDC_FLAG_TIMING | SDC_FLAG_CONNECTED           */
+    int32_t flags;         /* SDC_FLAG_TIMING | SDC_FLAG_CONNECTED |
+                              SDC_FLAG_NO_KEY_TABLE                          */
 } sdc_corr_spec;
 
 /* flags: record HIP events around each kernel of sdc_accumulate (on the
@@ -113,6 +114,13 @@ typedef struct {
  * to zero over the origins).  The self term and the site sum (C_sum) are
  * connected the same way. */
 #define SDC_FLAG_CONNECTED 2
+/* flags: radial bins only.  By default a plan stores the shell of every
+ * ordered pair (2 bytes per pair slot, 8 KiB per pair of 64-point tiles,
+ * 8.6 GB for 65536 points) when that is at most 32 GiB and a quarter of the
+ * free device memory, computed once at creation; the fused epilogue then
+ * reads it instead of recomputing distances for every lag group.  This flag
+ * keeps the on-the-fly computation (no table). */
+#define SDC_FLAG_NO_KEY_TABLE 4
 
 typedef struct sdc_plan sdc_plan;
 

@@ -90,6 +90,9 @@ std::vector<KGroup> make_groups(const std::vector<int>& lags, int s, int lg) {
 
 sdc_status sdc::set_error(sdc_status s, const std::string& msg) { return set_err(s, msg); }
 
+// Largest radial key table kept per plan (2 bytes per ordered tile-pair slot).
+constexpr size_t kMaxKeyTableBytes = (size_t)32 << 30;
+
 struct LagSel {
     KGroup* d_groups = nullptr;
     int n_groups = 0;
@@ -120,6 +123,7 @@ struct sdc_plan {
     double* d_msum = nullptr;    // [n_lags] sum_o M . M (site-summed raw correlation)
     double* d_mframe = nullptr;  // [t_req][3] per-frame site sums (scratch)
     float* d_mean = nullptr;     // [n][4] origin averages (connected form, scratch)
+    uint16_t* d_keys = nullptr;  // radial: per-pair shell tiles, 8 KiB per tile pair
     double* d_C = nullptr;
     double* d_fin = nullptr;  // csum, cself, ssum[2], sself[2]
     void* d_A = nullptr;
@@ -191,7 +195,7 @@ sdc_status check_specs(const sdc_bin_spec* bins, const sdc_corr_spec* corr) {
         return set_err(SDC_ERR_INVALID_ARG, "origin_stride must be in [1, 64]");
     if (corr->precision < SDC_PREC_FP32 || corr->precision > SDC_PREC_BF16X3)
         return set_err(SDC_ERR_INVALID_ARG, "unknown precision");
-    if ((corr->flags & ~(SDC_FLAG_TIMING | SDC_FLAG_CONNECTED)) != 0)
+    if ((corr->flags & ~(SDC_FLAG_TIMING | SDC_FLAG_CONNECTED | SDC_FLAG_NO_KEY_TABLE)) != 0)
         return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
     if (bins->kind < SDC_BINS_PERIODIC_SC || bins->kind > SDC_BINS_RADIAL)
         return set_err(SDC_ERR_INVALID_ARG, "unknown bin kind");
@@ -221,6 +225,7 @@ sdc_status fused_args(const sdc_plan* p, const LagSel& sel, sdc::FusedArgs* a) {
     a->n_groups = sel.n_groups;
     a->gtab = p->d_gtab;
     a->pos4 = p->d_pos4;
+    a->keys = p->d_keys;
     a->e2 = p->d_e2;
     a->n_shells = L.n_shells;
     a->inv_w = L.n_shells ? (float)((double)L.n_shells / (double)p->bins.r_max) : 0.0f;
@@ -522,6 +527,21 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     if (e != 0) {
         delete p;
         return hip_err(e, "count kernel");
+    }
+    // Radial: the shells of every tile pair, once, for all lag groups of all
+    // accumulates (2 bytes per ordered pair), when the table fits the budget.
+    if (L.kind == SDC_BINS_RADIAL && !(corr->flags & SDC_FLAG_NO_KEY_TABLE)) {
+        const size_t bytes = L.pairs.size() * (size_t)sdc::kTile * sdc::kTile * sizeof(uint16_t);
+        size_t free_b = 0, total_b = 0;
+        TRYHIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        if (bytes <= kMaxKeyTableBytes && bytes <= free_b / 4) {
+            TRY(dalloc((char**)&p->d_keys, bytes, &p->owned));
+            e = sdc::launch_radial_keys(ca, (int64_t)L.pairs.size(), p->d_keys, nullptr);
+            if (e != 0) {
+                delete p;
+                return hip_err(e, "radial key kernel");
+            }
+        }
     }
     TRYHIP(hipDeviceSynchronize(), "count kernel");
 #undef TRY

@@ -165,6 +165,7 @@ struct FusedArgs {
     int n_groups;
     const int32_t* gtab;
     const float* pos4;
+    const uint16_t* keys;          // radial: per-pair key tiles, or null (computed in the epilogue)
     const float* e2;
     int n_shells;
     float inv_w;
@@ -207,6 +208,9 @@ struct CountArgs {
     unsigned long long* counts;
 };
 int launch_count(const CountArgs& a, void* stream);
+// Radial key table: keys[((p*4 + wave)*64 + lane)*16 + r] = shell of the pair
+// element that accumulator register r of that lane holds for tile pair p.
+int launch_radial_keys(const CountArgs& a, int64_t n_pairs, uint16_t* keys, void* stream);
 
 struct SelfArgs {
     const float* frames;

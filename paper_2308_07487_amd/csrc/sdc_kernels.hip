@@ -449,12 +449,21 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         const int64_t rowbase = (int64_t)pr.ti * kTile + wi * 32 + 4 * h;
         int bin[16];
         if constexpr (RADIAL) {
-            const float4 pj = *(const float4*)(a.pos4 + 4 * sj);
+            if (a.keys) {
+                // the pair's shells, computed once per plan for all lag groups
+                const uint4* kp = (const uint4*)(a.keys + (((int64_t)p * 4 + wave) * 64 + lane) * 16);
+                const uint4 k0 = kp[0], k1 = kp[1];
+                const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float4 pi = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
-                const float d2 = dist2_f32(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
-                bin[r] = shell_of(d2, e2s, a.n_shells, a.inv_w);
+                for (int r = 0; r < 16; ++r) bin[r] = (int)((kw[r / 2] >> (16 * (r & 1))) & 0xFFFFu);
+            } else {
+                const float4 pj = *(const float4*)(a.pos4 + 4 * sj);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float4 pi = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
+                    const float d2 = dist2_f32(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
+                    bin[r] = shell_of(d2, e2s, a.n_shells, a.inv_w);
+                }
             }
         } else {
             const int gj = a.gtab[sj] + pr.shift;
@@ -716,6 +725,44 @@ __global__ __launch_bounds__(256) void count_kernel(CountArgs a) {
         }
         atomicAdd(&a.counts[b], (unsigned long long)v);
     }
+}
+
+// One workgroup per tile pair; thread (wave, lane) writes the 16 shells its
+// accumulator registers hold in the fused kernel (same row/column mapping).
+__global__ __launch_bounds__(256) void radial_keys_kernel(CountArgs a, int64_t n_pairs, uint16_t* __restrict__ keys) {
+    __shared__ float e2s[1024];
+    const int tid = threadIdx.x;
+    for (int x = tid; x < a.n_shells; x += 256) e2s[x] = a.e2[x];
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wi = wave >> 1, wj = wave & 1, h = lane >> 5, l32 = lane & 31;
+    for (int64_t p = blockIdx.x; p < n_pairs; p += gridDim.x) {
+        const KPair pr = a.pairs[p];
+        const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
+        const int64_t rowbase = (int64_t)pr.ti * kTile + wi * 32 + 4 * h;
+        const float4 pj = *(const float4*)(a.pos4 + 4 * sj);
+        uint32_t kw[8];
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+            const float4 p0 = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
+            const float4 p1 = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * ((r + 1) / 4) + ((r + 1) % 4)));
+            const uint32_t k0 = (uint32_t)shell_of(dist2_f32(p0.x, p0.y, p0.z, pj.x, pj.y, pj.z), e2s, a.n_shells, a.inv_w);
+            const uint32_t k1 = (uint32_t)shell_of(dist2_f32(p1.x, p1.y, p1.z, pj.x, pj.y, pj.z), e2s, a.n_shells, a.inv_w);
+            kw[r / 2] = k0 | (k1 << 16);
+        }
+        uint4* dst = (uint4*)(keys + ((p * 4 + wave) * 64 + lane) * 16);
+        dst[0] = make_uint4(kw[0], kw[1], kw[2], kw[3]);
+        dst[1] = make_uint4(kw[4], kw[5], kw[6], kw[7]);
+    }
+}
+
+int launch_radial_keys(const CountArgs& a, int64_t n_pairs, uint16_t* keys, void* stream) {
+    if (n_pairs == 0) return 0;
+    if (a.n_shells > 1024) return (int)hipErrorInvalidValue;
+    const int64_t grid = n_pairs < 65536 ? n_pairs : 65536;
+    hipLaunchKernelGGL(radial_keys_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, a, n_pairs,
+                       keys);
+    return (int)hipGetLastError();
 }
 
 int launch_count(const CountArgs& a, void* stream) {

@@ -310,3 +310,24 @@ def test_connected_static_is_zero(torch_dev, S, prec):
     assert np.max(np.abs(out["C"])) == 0.0
     assert np.max(np.abs(out["Cself"])) == 0.0
     assert np.max(np.abs(out["Csum"])) < 1e-12
+
+
+def test_radial_key_table_and_on_the_fly_agree(torch_dev, S, orc):
+    """The stored per-pair shells and the epilogue's own distance computation
+    give the same bins (and both match the oracle)."""
+    _say("radial key table vs on-the-fly shells")
+    pos = inputs.ball_positions(900, 6.0, 17)
+    n_o, n_L = 12, 10
+    fr = inputs.random_unit_frames(n_o + n_L - 1, pos.shape[0], seed=5)
+    outs = []
+    for table in (True, False):
+        with S.Plan(pos, S.BINS_RADIAL, n_o, n_L, "split_bf16", n_shells=300, r_max=13.0,
+                    key_table=table) as p:
+            p.accumulate(torch_dev.from_numpy(fr).cuda())
+            outs.append((p.finalize(), p.raw()[0]))
+    np.testing.assert_array_equal(outs[0][0]["counts"], outs[1][0]["counts"])
+    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-12, atol=1e-12 * np.max(np.abs(outs[1][1])))
+    Hr, cr = orc.binned_corr(pos, fr, orc.RADIAL, n_o, np.arange(n_L), n_shells=300, r_max=13.0)
+    np.testing.assert_array_equal(outs[0][0]["counts"], cr)
+    C, *_ = orc.finalize(Hr, cr, pos.shape[0], float(n_o), orc.self_corr(fr, n_o, np.arange(n_L)))
+    assert _normwise(outs[0][0]["C"], C) <= _tol_random("split_bf16", cr, n_o)

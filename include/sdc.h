@@ -187,6 +187,24 @@ sdc_status sdc_finalize(sdc_plan* plan, double* C_host, uint64_t* counts_host,
                         double* Sself_host, void* stream);
 
 /*
+ * Dynamic structure factor of Eq. (3) from the accumulated bins of a
+ * periodic plan (sc or bcc), on the GPU in FP64, then the windowed time
+ * transform of Sec. 2.2 (the window of sdc_finalize):
+ *     S(q, t) = (1 / (N n_org[t])) sum_b exp(-i q.d_b) H[t][b],
+ * d_b the displacement of bin b (bcc: plus half a cell on every axis for
+ * the odd parity), q_a = 2 pi m_a / L_a with integer m (the wave vectors
+ * commensurate with the box; for these the bins give Eq. (3) exactly).
+ *  m_host   : [n_q][3] int32, |m| <= 2^20, host.
+ *  Sqt_host : [n_q][n_lags][2] (re, im) or NULL.
+ *  Sqw_host : [n_q][n_lags][2] (re, im) of sum_t w_t S(q,t) e^{-2 pi i k t/n_lags},
+ *             or NULL (not both NULL).
+ * Synchronises the stream; allocates and frees its own scratch.
+ * Errors: INVALID_ARG, UNSUPPORTED (radial plan), STATE, OOM, HIP.
+ */
+sdc_status sdc_plan_structure_factor(sdc_plan* plan, const int32_t* m_host, int32_t n_q,
+                                     double* Sqt_host, double* Sqw_host, void* stream);
+
+/*
  * Raw accumulated state (for exact comparisons and checkpointing): H
  * [n_lags][n_bins] FP64, per-lag origin totals [n_lags] FP64, raw self sums
  * [n_lags] FP64, raw site sums sum_o M.M [n_lags] FP64.  Any output may be

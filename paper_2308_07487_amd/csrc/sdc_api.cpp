@@ -640,6 +640,63 @@ sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, doub
     return SDC_OK;
 }
 
+sdc_status sdc_plan_structure_factor(sdc_plan* p, const int32_t* m_host, int32_t n_q, double* Sqt_host,
+                                     double* Sqw_host, void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    if (!m_host || (!Sqt_host && !Sqw_host)) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    if (n_q < 1 || n_q > 65535) return set_err(SDC_ERR_INVALID_ARG, "n_q must be in [1, 65535]");
+    if (p->lay.kind == SDC_BINS_RADIAL)
+        return set_err(SDC_ERR_UNSUPPORTED, "S(q, t) from bins needs a periodic plan");
+    for (int64_t x = 0; x < 3 * (int64_t)n_q; ++x)
+        if (m_host[x] < -(1 << 20) || m_host[x] > (1 << 20))
+            return set_err(SDC_ERR_INVALID_ARG, "wave-vector index out of range");
+    SDC_HIP(select_device(p->device), "hipSetDevice");
+    const int nl = p->corr.n_lags;
+    const size_t out_n = (size_t)n_q * nl * 2;
+    std::vector<void*> tmp;
+    int32_t* d_m = nullptr;
+    double* d_out = nullptr;
+    s = dalloc(&d_m, (size_t)3 * n_q, &tmp);
+    if (s == SDC_OK) s = dalloc(&d_out, 2 * out_n, &tmp);
+    auto release = [&]() {
+        for (void* q : tmp) (void)hipFree(q);
+    };
+    if (s != SDC_OK) {
+        release();
+        return s;
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t he = hipMemcpyAsync(d_m, m_host, (size_t)3 * n_q * sizeof(int32_t), hipMemcpyHostToDevice, hs);
+    sdc::SqtArgs a{};
+    a.H = p->d_H;
+    a.n_org = p->d_norg;
+    a.n_bins = p->lay.n_bins;
+    a.n_sites = p->lay.n;
+    a.n_lags = nl;
+    a.kind = p->lay.kind;
+    a.L0 = p->lay.L[0];
+    a.L1 = p->lay.L[1];
+    a.L2 = p->lay.L[2];
+    a.m = d_m;
+    a.n_q = n_q;
+    a.sqt = d_out;
+    a.sqw = d_out + out_n;
+    int e = he == hipSuccess ? sdc::launch_sqt(a, stream) : (int)he;
+    if (e == 0 && Sqt_host)
+        e = (int)hipMemcpyAsync(Sqt_host, a.sqt, out_n * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == 0 && Sqw_host)
+        e = (int)hipMemcpyAsync(Sqw_host, a.sqw, out_n * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == 0) e = (int)hipStreamSynchronize(hs);
+    release();
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "structure factor");
+    }
+    return SDC_OK;
+}
+
 sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double* self_host, double* msum_host,
                         void* stream) {
     g_err.clear();

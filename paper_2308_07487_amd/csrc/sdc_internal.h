@@ -249,6 +249,21 @@ struct FinalArgs {
 };
 int launch_finalize(const FinalArgs& a, void* stream);
 
+// S(q, t) of Eq. (3) from the bins of a periodic plan, for wave vectors
+// q_a = 2 pi m_a / L_a (integer m), and its windowed time transform.
+struct SqtArgs {
+    const double* H;       // [n_lags][n_bins]
+    const double* n_org;   // [n_lags]
+    int64_t n_bins, n_sites;
+    int n_lags;
+    int kind, L0, L1, L2;  // periodic bin enumeration (sc / bcc)
+    const int32_t* m;      // [n_q][3]
+    int n_q;
+    double* sqt;           // [n_q][n_lags][2]
+    double* sqw;           // [n_q][n_lags][2]
+};
+int launch_sqt(const SqtArgs& a, void* stream);
+
 int launch_zero(void* ptr, int64_t bytes, void* stream);
 
 struct TrajArgs {

@@ -1065,6 +1065,78 @@ __global__ void dft_kernel(FinalArgs a) {
     a.sself[2 * k + 1] = im1;
 }
 
+// One workgroup per (q, lag): S(q, t) = sum_b exp(-i q.d_b) H(b, t) / (N n_org),
+// d_b the displacement of bin b (bcc: the parity adds half a cell on every
+// axis).  FP64 throughout; the phase is reduced exactly in integers first.
+__global__ __launch_bounds__(256) void sqt_kernel(SqtArgs a) {
+    __shared__ double red[2][256];
+    const int qi = blockIdx.x, t = blockIdx.y;
+    const int64_t m0 = a.m[3 * qi], m1 = a.m[3 * qi + 1], m2 = a.m[3 * qi + 2];
+    const bool bcc = a.kind == SDC_BINS_PERIODIC_BCC;
+    double re = 0.0, im = 0.0;
+    for (int64_t b = threadIdx.x; b < a.n_bins; b += 256) {
+        const int64_t c = bcc ? b >> 1 : b;
+        const int par = bcc ? (int)(b & 1) : 0;
+        const int64_t k0 = c / ((int64_t)a.L1 * a.L2), k1 = (c / a.L2) % a.L1, k2 = c % a.L2;
+        // q.d / pi = sum_a 2 m_a (k_a + p/2) / L_a = sum_a m_a (2 k_a + p) / L_a, taken mod 2
+        // per axis in integers: m_a (2 k_a + p) mod 2 L_a
+        const int64_t n0 = (m0 * (2 * k0 + par)) % (2 * (int64_t)a.L0);
+        const int64_t n1 = (m1 * (2 * k1 + par)) % (2 * (int64_t)a.L1);
+        const int64_t n2 = (m2 * (2 * k2 + par)) % (2 * (int64_t)a.L2);
+        const double x = (double)n0 / a.L0 + (double)n1 / a.L1 + (double)n2 / a.L2;
+        double sn, cs;
+        sincospi(-x, &sn, &cs);
+        const double h = a.H[(int64_t)t * a.n_bins + b];
+        re += cs * h;
+        im += sn * h;
+    }
+    red[0][threadIdx.x] = re;
+    red[1][threadIdx.x] = im;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double d = (double)a.n_sites * a.n_org[t];
+        const int64_t o = ((int64_t)qi * a.n_lags + t) * 2;
+        a.sqt[o] = d > 0.0 ? red[0][0] / d : 0.0;
+        a.sqt[o + 1] = d > 0.0 ? red[1][0] / d : 0.0;
+    }
+}
+
+// Windowed DFT over the lags of each q (same window as the site sums).
+__global__ void sqw_kernel(SqtArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int qi = blockIdx.y;
+    const int m = a.n_lags;
+    if (k >= m) return;
+    const double* x = a.sqt + (int64_t)qi * m * 2;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < m; ++t) {
+        const double w = 0.5 * (1.0 + cospi((double)t / (double)m));
+        const int64_t kt = ((int64_t)k * t) % m;
+        double sn, cs;
+        sincospi(-2.0 * (double)kt / (double)m, &sn, &cs);
+        // (x_re + i x_im)(cs + i sn)
+        re += w * (x[2 * t] * cs - x[2 * t + 1] * sn);
+        im += w * (x[2 * t] * sn + x[2 * t + 1] * cs);
+    }
+    a.sqw[((int64_t)qi * m + k) * 2] = re;
+    a.sqw[((int64_t)qi * m + k) * 2 + 1] = im;
+}
+
+int launch_sqt(const SqtArgs& a, void* stream) {
+    if (a.n_q == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(sqt_kernel, dim3((unsigned)a.n_q, (unsigned)a.n_lags), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sqw_kernel, dim3((unsigned)((a.n_lags + 63) / 64), (unsigned)a.n_q), dim3(64), 0, s, a);
+    return (int)hipGetLastError();
+}
+
 int launch_finalize(const FinalArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     if (a.C) {

@@ -55,7 +55,7 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset", "sdc_plan_destroy",
            "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate",
            "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_timings", "sdc_batch_info",
-           "sdc_batch_destroy")
+           "sdc_batch_destroy", "sdc_plan_structure_factor")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -93,6 +93,7 @@ def lib():
         L.sdc_batch_accumulate.argtypes = [P, P, P, P]
         L.sdc_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.sdc_batch_destroy.argtypes = [P]
+        L.sdc_plan_structure_factor.argtypes = [P, P, i32, P, P, P]
         for name in EXPORTS:
             if name not in ("sdc_status_string", "sdc_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -237,6 +238,18 @@ class Plan:
         msum = np.ascontiguousarray(msum, dtype=np.float64)
         _check(lib().sdc_plan_load_raw(self._h, _np_ptr(H), _np_ptr(n_org), _np_ptr(self_raw), _np_ptr(msum),
                                        _stream_ptr(stream)), "sdc_plan_load_raw")
+
+    def structure_factor(self, m, stream=None):
+        """S(q, t) and its windowed transform for q_a = 2 pi m_a / L_a (periodic
+        plans): returns (Sqt [n_q][n_lags], Sqw [n_q][n_lags]), complex128."""
+        m = np.ascontiguousarray(np.atleast_2d(m), dtype=np.int32)
+        if m.shape[1] != 3:
+            raise ValueError("m must have shape [n_q][3]")
+        sqt = np.zeros((m.shape[0], self.n_lags, 2))
+        sqw = np.zeros((m.shape[0], self.n_lags, 2))
+        _check(lib().sdc_plan_structure_factor(self._h, _np_ptr(m), m.shape[0], _np_ptr(sqt), _np_ptr(sqw),
+                                               _stream_ptr(stream)), "sdc_plan_structure_factor")
+        return sqt[..., 0] + 1j * sqt[..., 1], sqw[..., 0] + 1j * sqw[..., 1]
 
     def timings(self):
         """(pack_ms, self_ms, fused_ms) of the last accumulate (timing plans only)."""

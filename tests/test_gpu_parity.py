@@ -331,3 +331,35 @@ def test_radial_key_table_and_on_the_fly_agree(torch_dev, S, orc):
     np.testing.assert_array_equal(outs[0][0]["counts"], cr)
     C, *_ = orc.finalize(Hr, cr, pos.shape[0], float(n_o), orc.self_corr(fr, n_o, np.arange(n_L)))
     assert _normwise(outs[0][0]["C"], C) <= _tol_random("split_bf16", cr, n_o)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("lat", ["sc", "bcc"])
+def test_structure_factor_matches_oracle(torch_dev, S, orc, prec, lat):
+    """S(q, t) of Eq. (3) from the GPU bins against the oracle's direct double
+    sum over site pairs, and its windowed transform against the oracle DFT."""
+    _say(f"structure factor {lat} {prec}")
+    L = (5, 4, 6) if lat == "sc" else (3, 4, 3)
+    pos = inputs.sc_positions(L) if lat == "sc" else inputs.bcc_positions(L)
+    kind = S.BINS_SC if lat == "sc" else S.BINS_BCC
+    pos, _, _ = inputs.permute_sites(pos, np.zeros((1, pos.shape[0], 3), np.float32), seed=9)
+    n_o, n_L = 10, 12
+    fr = inputs.random_unit_frames(n_o + n_L - 1, pos.shape[0], seed=19)
+    ms = np.array([[0, 0, 0], [1, 0, 0], [2, 1, 3], [-1, 2, 1], [5, 4, 6]], dtype=np.int32)
+    with S.Plan(pos, kind, n_o, n_L, prec, cells=L) as p:
+        p.accumulate(torch_dev.from_numpy(fr).cuda())
+        sqt, sqw = p.structure_factor(ms)
+    ref = orc.structure_factor(pos, fr, n_o, list(range(n_L)), ms, L)
+    scale = max(1.0, float(np.max(np.abs(ref))))
+    e = float(np.max(np.abs(sqt - ref))) / scale
+    # S sums every pair once: split-BF16's unbiased per-product noise
+    # (2^-17) averages only over the origins, so its bar is statistical
+    bar = 1e-6 if prec != "split_bf16" else max(1e-6, 6 * 2.0 ** -17 / np.sqrt(n_o))
+    print(f"  S(q,t) error {e:.3e} (bar {bar:.2e})", flush=True)
+    assert e <= bar
+    for qi in range(ms.shape[0]):
+        w_ref = orc.dft(ref[qi].real) + 1j * orc.dft(ref[qi].imag)
+        assert np.max(np.abs(sqw[qi] - w_ref)) <= bar * scale * n_L
+    with pytest.raises(S.SdcError):
+        with S.Plan(inputs.ball_positions(64, 2.0, 1), S.BINS_RADIAL, 4, 4, prec, n_shells=8, r_max=4.0) as pr:
+            pr.structure_factor(ms)

@@ -561,3 +561,47 @@ def test_connected_self_and_select_consistent(orc):
     bins = np.array([0, 5, 7, 23])
     Hs, _ = orc.binned_corr_select(pos, fr, orc.SC, 7, lags, bins, cells=L, connected=True)
     np.testing.assert_allclose(Hs, H[:, bins], rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# structure factor, Eq. (3)
+# --------------------------------------------------------------------------
+
+def test_structure_factor_planted_spiral_closed_form(orc):
+    """S_i(t) a spin wave with wave vector q0 and frequency w: Eq. (3) gives
+    S(q0, t) = (N / 2) sin^2(theta) exp(-i w t) exactly (2 q0 not a reciprocal
+    lattice vector), and zero at a q that is neither 0 nor +-q0."""
+    L = (6, 4, 5)
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    m0 = np.array([1, 1, 2])
+    q0 = 2 * np.pi * m0 / np.array(L)
+    theta, omega, dt = 1.1, 0.7, 0.1
+    n_o, lags = 6, [0, 1, 4]
+    fr = inputs.spiral_frames(pos, q0, theta, omega, n_o + max(lags), dt)
+    S = orc.structure_factor(pos, fr, n_o, lags, [m0, [2, 1, 1]], L)
+    ref = 0.5 * n * np.sin(theta) ** 2 * np.exp(-1j * omega * dt * np.array(lags))
+    np.testing.assert_allclose(S[0], ref, rtol=2e-6, atol=2e-6 * n)
+    assert np.max(np.abs(S[1])) < 2e-6 * n
+
+
+def test_structure_factor_matches_bins(orc):
+    """The bins carry Eq. (3) for commensurate q: sum_b exp(-i q.d_b) H(b, t)
+    / (N n_o) equals the direct double sum (bcc: half-cell offsets)."""
+    L = (3, 2, 3)
+    pos = inputs.bcc_positions(L)
+    n = pos.shape[0]
+    fr = inputs.random_unit_frames(9, n, seed=2)
+    n_o, lags = 4, [0, 2, 5]
+    ms = np.array([[1, 0, 2], [0, 1, 1], [2, 1, 0]])
+    S = orc.structure_factor(pos, fr, n_o, lags, ms, L)
+    H, _ = orc.binned_corr(pos, fr, orc.BCC, n_o, lags, cells=L)
+    nsc = int(np.prod(L))
+    b = np.arange(2 * nsc)
+    c, par = b // 2, b % 2
+    k = np.stack([c // (L[1] * L[2]), (c // L[2]) % L[1], c % L[2]], axis=1).astype(np.float64)
+    d = k + 0.5 * par[:, None]
+    for qi, mq in enumerate(ms):
+        q = 2 * np.pi * mq / np.array(L)
+        ph = np.exp(-1j * (d @ q))
+        np.testing.assert_allclose((H @ ph) / (n * n_o), S[qi], rtol=1e-12, atol=1e-12)

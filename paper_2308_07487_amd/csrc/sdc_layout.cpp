@@ -32,11 +32,45 @@ sdc_status fail(std::string* err, sdc_status s, const std::string& msg) {
     return s;
 }
 
-// Even chunking of [0, L) into ceil(L/4) chunks of size <= 4.
-void chunks(int L, std::vector<int>* start) {
-    int nb = (L + 3) / 4;
+// Even chunking of [0, L) into nb chunks (sizes floor or ceil of L / nb).
+void chunks(int L, int nb, std::vector<int>* start) {
     start->resize(nb + 1);
     for (int k = 0; k <= nb; ++k) (*start)[k] = (int)(((int64_t)k * L) / nb);
+}
+
+// Brick shape: chunk counts per axis such that a brick (at most
+// ceil(L_a / nb_a) cells per axis) fits a 64-slot tile.  The product costs
+// O(tiles^2), so the fewest tiles win; ties go to the smaller histogram
+// window, then to the shape closest to 4 x 4 x 4.  Edges that are multiples
+// of 4 keep 4 x 4 x 4 bricks with no padding; other edges avoid the up to
+// 2.4x padding of fixed 4-cell chunks (a 10^3 box: 20 tiles of 5 x 5 x 2
+// instead of 27 tiles of 4 x 4 x 4 slots).
+void choose_bricks(const int L[3], int nb[3]) {
+    int64_t best_tiles = -1, best_win = 0, best_dev = 0;
+    for (int s0 = 1; s0 <= std::min(L[0], kTile); ++s0) {
+        const int n0 = (L[0] + s0 - 1) / s0, m0 = (L[0] + n0 - 1) / n0;
+        if (m0 != s0) continue;  // every chunk count once, by its largest chunk
+        for (int s1 = 1; s1 <= std::min(L[1], kTile / s0); ++s1) {
+            const int n1 = (L[1] + s1 - 1) / s1, m1 = (L[1] + n1 - 1) / n1;
+            if (m1 != s1) continue;
+            for (int s2 = 1; s2 <= std::min(L[2], kTile / (s0 * s1)); ++s2) {
+                const int n2 = (L[2] + s2 - 1) / s2, m2 = (L[2] + n2 - 1) / n2;
+                if (m2 != s2) continue;
+                const int64_t tiles = (int64_t)n0 * n1 * n2;
+                const int64_t win = (int64_t)(2 * s0) * (2 * s1) * (2 * s2);
+                const int64_t dev = std::abs(s0 - 4) + std::abs(s1 - 4) + std::abs(s2 - 4);
+                if (best_tiles < 0 || tiles < best_tiles || (tiles == best_tiles && win < best_win) ||
+                    (tiles == best_tiles && win == best_win && dev < best_dev)) {
+                    best_tiles = tiles;
+                    best_win = win;
+                    best_dev = dev;
+                    nb[0] = n0;
+                    nb[1] = n1;
+                    nb[2] = n2;
+                }
+            }
+        }
+    }
 }
 
 uint64_t spread3(uint64_t v) {
@@ -90,9 +124,9 @@ sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec,
     std::vector<int> st[3];
     std::vector<int> chunk_of[3];
     int nb[3], maxsz[3];
+    choose_bricks(L, nb);
     for (int a = 0; a < 3; ++a) {
-        chunks(L[a], &st[a]);
-        nb[a] = (int)st[a].size() - 1;
+        chunks(L[a], nb[a], &st[a]);
         maxsz[a] = 0;
         chunk_of[a].assign(L[a], 0);
         for (int k = 0; k < nb[a]; ++k) {
@@ -127,6 +161,16 @@ sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec,
     auto tile_of = [&](int beta, int k0, int k1, int k2) {
         return ((beta * nb[0] + k0) * nb[1] + k1) * nb[2] + k2;
     };
+    // slot q of a tile = brick cell (o0, o1, o2) with q = (o0 * s1 + o1) * s2 + o2,
+    // s = largest chunk per axis; its window coordinate does not depend on the
+    // tile, so padded slots (zero spins) get one in range as well
+    const int brick = maxsz[0] * maxsz[1] * maxsz[2];
+    for (int64_t p = 0; p < lay->n_pad; ++p) {
+        const int q = (int)(p % kTile);
+        if (q >= brick) continue;
+        const int o0 = q / (maxsz[1] * maxsz[2]), o1 = (q / maxsz[2]) % maxsz[1], o2 = q % maxsz[2];
+        lay->gtab[p] = (o0 * W1 + o1) * W2 + o2;
+    }
     for (int64_t i = 0; i < n; ++i) {
         int c[3], beta = 0;
         if (!bcc) {
@@ -156,10 +200,9 @@ sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec,
             k[a] = chunk_of[a][c[a]];
             o[a] = c[a] - st[a][k[a]];
         }
-        int64_t p = (int64_t)tile_of(beta, k[0], k[1], k[2]) * kTile + (o[0] * 4 + o[1]) * 4 + o[2];
+        int64_t p = (int64_t)tile_of(beta, k[0], k[1], k[2]) * kTile + (o[0] * maxsz[1] + o[1]) * maxsz[2] + o[2];
         if (lay->perm[p] >= 0) return fail(err, SDC_ERR_INVALID_ARG, "duplicate lattice site");
         lay->perm[p] = (int32_t)i;
-        lay->gtab[p] = (o[0] * W1 + o[1]) * W2 + o[2];
     }
     const int stride[3] = {W1 * W2, W2, 1};
     lay->streams.reserve((size_t)nsub * nsub * nbt);

@@ -100,7 +100,7 @@ typedef struct {
                            /* frame o*s; lag t pairs it with frame o*s + t)  */
     int32_t precision;     /* sdc_precision                                  */
     int32_t flags;         /* SDC_FLAG_TIMING | SDC_FLAG_CONNECTED |
-                              SDC_FLAG_NO_KEY_TABLE                          */
+                              SDC_FLAG_NO_KEY_TABLE | SDC_FLAG_DETERMINISTIC */
 } sdc_corr_spec;
 
 /* flags: record HIP events around each kernel of sdc_accumulate (on the
@@ -121,6 +121,15 @@ typedef struct {
  * reads it instead of recomputing distances for every lag group.  This flag
  * keeps the on-the-fly computation (no table). */
 #define SDC_FLAG_NO_KEY_TABLE 4
+/* flags: deterministic results.  Every sum that several threads add into
+ * (the per-task histograms, the global bins, the self sums) is kept as a
+ * 64-bit two's-complement fixed-point number with 2^-20 resolution, so the
+ * integer atomics give bit-identical bins, self sums and outputs whatever the
+ * order of the adds; each added value is rounded once to 2^-20 (about 1e-6
+ * absolute, far below the FP32 product's own rounding for |G| > 1).  Range:
+ * |H[t][b]| < 2^43 (8.8e12) over all accumulates.  The FP64 views are
+ * refreshed by sdc_finalize, sdc_plan_raw and sdc_plan_structure_factor. */
+#define SDC_FLAG_DETERMINISTIC 8
 
 typedef struct sdc_plan sdc_plan;
 

@@ -124,6 +124,8 @@ struct sdc_plan {
     double* d_mframe = nullptr;  // [t_req][3] per-frame site sums (scratch)
     float* d_mean = nullptr;     // [n][4] origin averages (connected form, scratch)
     uint16_t* d_keys = nullptr;  // radial: per-pair shell tiles, 8 KiB per tile pair
+    unsigned long long* d_Hq = nullptr;     // deterministic mode: fixed-point H
+    unsigned long long* d_selfq = nullptr;  // deterministic mode: fixed-point self sums
     double* d_C = nullptr;
     double* d_fin = nullptr;  // csum, cself, ssum[2], sself[2]
     void* d_A = nullptr;
@@ -195,7 +197,7 @@ sdc_status check_specs(const sdc_bin_spec* bins, const sdc_corr_spec* corr) {
         return set_err(SDC_ERR_INVALID_ARG, "origin_stride must be in [1, 64]");
     if (corr->precision < SDC_PREC_FP32 || corr->precision > SDC_PREC_BF16X3)
         return set_err(SDC_ERR_INVALID_ARG, "unknown precision");
-    if ((corr->flags & ~(SDC_FLAG_TIMING | SDC_FLAG_CONNECTED | SDC_FLAG_NO_KEY_TABLE)) != 0)
+    if ((corr->flags & ~(SDC_FLAG_TIMING | SDC_FLAG_CONNECTED | SDC_FLAG_NO_KEY_TABLE | SDC_FLAG_DETERMINISTIC)) != 0)
         return set_err(SDC_ERR_INVALID_ARG, "unknown flags");
     if (bins->kind < SDC_BINS_PERIODIC_SC || bins->kind > SDC_BINS_RADIAL)
         return set_err(SDC_ERR_INVALID_ARG, "unknown bin kind");
@@ -237,6 +239,8 @@ sdc_status fused_args(const sdc_plan* p, const LagSel& sel, sdc::FusedArgs* a) {
     a->W2 = L.W[2];
     a->win = L.win;
     a->H = p->d_H;
+    a->det = p->d_Hq != nullptr;
+    a->Hq = p->d_Hq;
     a->n_bins = L.n_bins;
     a->stride = p->corr.origin_stride;
     a->precision = p->corr.precision;
@@ -299,6 +303,9 @@ sdc_status queue_pack_self(sdc_plan* p, const LagSel& sel, const float* spins_de
     sa.mframe = p->d_mframe;
     sa.msum = p->d_msum;
     sa.mean = p->d_mean;
+    sa.det = p->d_Hq != nullptr;
+    sa.selfq = p->d_selfq;
+    sa.Hq = p->d_Hq;
     if (timing) SDC_HIP(hipEventRecord(p->ev[1], hs), "hipEventRecord");
     e = sdc::launch_self(sa, stream);
     if (e != 0) {
@@ -306,6 +313,15 @@ sdc_status queue_pack_self(sdc_plan* p, const LagSel& sel, const float* spins_de
         return hip_err(e, "self kernel");
     }
     return SDC_OK;
+}
+
+// Deterministic mode: refresh the FP64 views (H, self sums) from the
+// fixed-point accumulators, queued on the stream.
+int refresh_fixed(sdc_plan* p, void* stream) {
+    if (!p->d_Hq) return 0;
+    int e = sdc::launch_fixed_to_double(p->d_Hq, p->d_H, (int64_t)p->corr.n_lags * p->lay.n_bins, stream);
+    if (e == 0) e = sdc::launch_fixed_to_double(p->d_selfq, p->d_self, p->corr.n_lags, stream);
+    return e;
 }
 
 }  // namespace
@@ -484,6 +500,12 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     TRY(dalloc(&p->d_msum, (size_t)corr->n_lags, &p->owned));
     TRY(dalloc(&p->d_mframe, (size_t)p->t_req * 3, &p->owned));
     if (corr->flags & SDC_FLAG_CONNECTED) TRY(dalloc(&p->d_mean, (size_t)L.n * 4, &p->owned));
+    if (corr->flags & SDC_FLAG_DETERMINISTIC) {
+        TRY(dalloc(&p->d_Hq, (size_t)corr->n_lags * L.n_bins, &p->owned));
+        TRY(dalloc(&p->d_selfq, (size_t)corr->n_lags, &p->owned));
+        TRYHIP(hipMemset(p->d_Hq, 0, (size_t)corr->n_lags * L.n_bins * 8), "zero fixed-point H");
+        TRYHIP(hipMemset(p->d_selfq, 0, (size_t)corr->n_lags * 8), "zero fixed-point self sums");
+    }
     TRY(dalloc(&p->d_fin, (size_t)6 * corr->n_lags, &p->owned));
     TRY(dalloc((char**)&p->d_A, p->bytes_A, &p->owned));
     TRY(dalloc((char**)&p->d_B, p->bytes_B, &p->owned));
@@ -602,6 +624,13 @@ sdc_status sdc_finalize(sdc_plan* p, double* C_host, uint64_t* counts_host, doub
         s = dalloc(&p->d_C, (size_t)nl * L.n_bins, &p->owned);
         if (s != SDC_OK) return s;
     }
+    {
+        const int e = refresh_fixed(p, stream);
+        if (e != 0) {
+            p->failed = true;
+            return hip_err(e, "fixed-point conversion");
+        }
+    }
     sdc::FinalArgs fa{};
     fa.H = p->d_H;
     fa.counts = p->d_counts;
@@ -669,6 +698,7 @@ sdc_status sdc_plan_structure_factor(sdc_plan* p, const int32_t* m_host, int32_t
     }
     hipStream_t hs = (hipStream_t)stream;
     hipError_t he = hipMemcpyAsync(d_m, m_host, (size_t)3 * n_q * sizeof(int32_t), hipMemcpyHostToDevice, hs);
+    if (he == hipSuccess) he = (hipError_t)refresh_fixed(p, stream);
     sdc::SqtArgs a{};
     a.H = p->d_H;
     a.n_org = p->d_norg;
@@ -705,6 +735,13 @@ sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double*
     SDC_HIP(select_device(p->device), "hipSetDevice");
     hipStream_t hs = (hipStream_t)stream;
     const int nl = p->corr.n_lags;
+    {
+        const int e = refresh_fixed(p, stream);
+        if (e != 0) {
+            p->failed = true;
+            return hip_err(e, "fixed-point conversion");
+        }
+    }
     if (H_host)
         SDC_HIP(hipMemcpyAsync(H_host, p->d_H, (size_t)nl * p->lay.n_bins * 8, hipMemcpyDeviceToHost, hs), "copy H");
     if (self_host) SDC_HIP(hipMemcpyAsync(self_host, p->d_self, (size_t)nl * 8, hipMemcpyDeviceToHost, hs), "copy self");
@@ -735,6 +772,14 @@ sdc_status sdc_plan_load_raw(sdc_plan* p, const double* H_host, const double* n_
     SDC_HIP(hipMemcpyAsync(p->d_self, self_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load self");
     SDC_HIP(hipMemcpyAsync(p->d_norg, n_org_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load origin totals");
     SDC_HIP(hipMemcpyAsync(p->d_msum, msum_host, (size_t)nl * 8, hipMemcpyHostToDevice, hs), "load site sums");
+    if (p->d_Hq) {
+        int e = sdc::launch_double_to_fixed(p->d_H, p->d_Hq, (int64_t)nl * p->lay.n_bins, stream);
+        if (e == 0) e = sdc::launch_double_to_fixed(p->d_self, p->d_selfq, nl, stream);
+        if (e != 0) {
+            p->failed = true;
+            return hip_err(e, "fixed-point conversion");
+        }
+    }
     hipError_t se = hipStreamSynchronize(hs);
     if (se != hipSuccess) {
         p->failed = true;
@@ -768,6 +813,8 @@ sdc_status sdc_plan_reset(sdc_plan* p, void* stream) {
     if (e == 0) e = sdc::launch_zero(p->d_self, (int64_t)p->corr.n_lags * 8, stream);
     if (e == 0) e = sdc::launch_zero(p->d_norg, (int64_t)p->corr.n_lags * 8, stream);
     if (e == 0) e = sdc::launch_zero(p->d_msum, (int64_t)p->corr.n_lags * 8, stream);
+    if (e == 0 && p->d_Hq) e = sdc::launch_zero(p->d_Hq, (int64_t)p->corr.n_lags * p->lay.n_bins * 8, stream);
+    if (e == 0 && p->d_selfq) e = sdc::launch_zero(p->d_selfq, (int64_t)p->corr.n_lags * 8, stream);
     if (e != 0) {
         p->failed = true;
         return hip_err(e, "reset");

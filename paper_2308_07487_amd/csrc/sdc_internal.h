@@ -171,6 +171,8 @@ struct FusedArgs {
     float inv_w;
     int kind, L0, L1, L2, W1, W2, win;
     double* H;
+    int det;                       // deterministic mode: fixed-point bins in Hq
+    unsigned long long* Hq;
     int64_t n_bins;
     int stride;
     int precision;
@@ -227,6 +229,9 @@ struct SelfArgs {
     double* mframe;       // [t_need][3] scratch: site-summed spin of each frame
     double* msum;         // [n_lags] += sum_o M(o s) . M(o s + t)
     const float* mean;    // [n][4] origin averages (connected form), or null
+    int det;              // deterministic mode: fixed-point self sums and bins
+    unsigned long long* selfq;
+    unsigned long long* Hq;
 };
 int launch_self(const SelfArgs& a, void* stream);
 // Per-site averages over the origins of one accumulate (connected form):
@@ -265,6 +270,13 @@ struct SqtArgs {
 int launch_sqt(const SqtArgs& a, void* stream);
 
 int launch_zero(void* ptr, int64_t bytes, void* stream);
+
+// Deterministic mode: every sum that several threads add into is kept as a
+// two's-complement 64-bit fixed-point number with 2^-20 resolution, so
+// integer atomics make the result independent of the order of the adds.
+constexpr double kFixedScale = 1048576.0;
+int launch_fixed_to_double(const unsigned long long* q, double* d, int64_t n, void* stream);
+int launch_double_to_fixed(const double* d, unsigned long long* q, int64_t n, void* stream);
 
 struct TrajArgs {
     int64_t n;

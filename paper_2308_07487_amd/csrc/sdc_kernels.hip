@@ -270,6 +270,11 @@ __device__ inline void f32_all(const float (&a)[8], const float (&w)[NF], f32x16
     (f32_q<Qs, NF, LG>(a, w, acc, std::make_integer_sequence<int, LG>{}), ...);
 }
 
+// Fixed-point image of v (deterministic mode), rounded to nearest.
+__device__ inline unsigned long long to_fixed(double v) {
+    return (unsigned long long)__double2ll_rn(v * kFixedScale);
+}
+
 __device__ inline int pmod_dev(int a, int m) {
     int r = a % m;
     return r < 0 ? r + m : r;
@@ -477,7 +482,10 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
                 for (int r = 0; r < 16; ++r) {
                     double v = (double)acc.v[m][r];
                     if constexpr (PREC == SDC_PREC_BF16X3) v += (double)acc.s[m][r];
-                    atomicAdd(&hist[m * a.win + bin[r]], v);
+                    if (a.det)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(hist) + m * a.win + bin[r], to_fixed(v));
+                    else
+                        atomicAdd(&hist[m * a.win + bin[r]], v);
                 }
             }
         }
@@ -489,7 +497,8 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         const int m = x / a.win;
         const int w = x - m * a.win;
         const double v = hist[x];
-        if (v != 0.0 && ((grp.mask >> m) & 1)) {
+        const unsigned long long vq = reinterpret_cast<const unsigned long long*>(hist)[x];
+        if (vq != 0ull && ((grp.mask >> m) & 1)) {
             int64_t b;
             if constexpr (RADIAL) {
                 b = w;
@@ -504,7 +513,10 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
                 if (a.kind == SDC_BINS_PERIODIC_BCC) b = 2 * b + st.parity;
             }
             const int64_t t = (int64_t)a.stride * (grp.u0 + m) + grp.phase;
-            unsafeAtomicAdd(&a.H[t * a.n_bins + b], v);
+            if (a.det)
+                atomicAdd(&a.Hq[t * a.n_bins + b], vq);
+            else
+                unsafeAtomicAdd(&a.H[t * a.n_bins + b], v);
         }
     }
 }
@@ -864,8 +876,14 @@ __global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_blo
                     if constexpr (PREC != SDC_PREC_FP32) sl += dropped_product<PREC>(u, x1[c]);
                 }
             }
-            atomicAdd(&part[l], s);
-            if constexpr (PREC != SDC_PREC_FP32) atomicAdd(&part_lo[l], sl);
+            if (a.det) {
+                atomicAdd(reinterpret_cast<unsigned long long*>(part) + l, to_fixed(s));
+                if constexpr (PREC != SDC_PREC_FP32)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(part_lo) + l, to_fixed(sl));
+            } else {
+                atomicAdd(&part[l], s);
+                if constexpr (PREC != SDC_PREC_FP32) atomicAdd(&part_lo[l], sl);
+            }
         }
     }
     __syncthreads();
@@ -874,8 +892,15 @@ __global__ __launch_bounds__(256) void self_kernel(SelfArgs a, int sites_per_blo
     if (blockIdx.x == 0)
         for (int l = tid; l < a.n_sel; l += 256) a.norg[a.lags[l]] += (double)a.n_origins;
     for (int l = tid; l < a.n_sel; l += 256) {
-        unsafeAtomicAdd(&a.self[a.lags[l]], part[l]);
-        if constexpr (PREC != SDC_PREC_FP32) unsafeAtomicAdd(&a.H[(int64_t)a.lags[l] * a.n_bins], part_lo[l]);
+        if (a.det) {
+            atomicAdd(&a.selfq[a.lags[l]], reinterpret_cast<const unsigned long long*>(part)[l]);
+            if constexpr (PREC != SDC_PREC_FP32)
+                atomicAdd(&a.Hq[(int64_t)a.lags[l] * a.n_bins], reinterpret_cast<const unsigned long long*>(part_lo)[l]);
+        } else {
+            unsafeAtomicAdd(&a.self[a.lags[l]], part[l]);
+            if constexpr (PREC != SDC_PREC_FP32)
+                unsafeAtomicAdd(&a.H[(int64_t)a.lags[l] * a.n_bins], part_lo[l]);
+        }
     }
 }
 
@@ -1154,6 +1179,33 @@ __global__ void zero_kernel(uint32_t* p, int64_t words) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < words;
          x += (int64_t)gridDim.x * blockDim.x)
         p[x] = 0u;
+}
+
+__global__ void fixed_to_double_kernel(const unsigned long long* __restrict__ q, double* __restrict__ d, int64_t n) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        d[x] = (double)(long long)q[x] / kFixedScale;
+}
+
+__global__ void double_to_fixed_kernel(const double* __restrict__ d, unsigned long long* __restrict__ q, int64_t n) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        q[x] = to_fixed(d[x]);
+}
+
+static int64_t grid_for(int64_t n) {
+    int64_t blocks = (n + 255) / 256;
+    return blocks > 8192 ? 8192 : (blocks < 1 ? 1 : blocks);
+}
+
+int launch_fixed_to_double(const unsigned long long* q, double* d, int64_t n, void* stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(fixed_to_double_kernel, dim3((unsigned)grid_for(n)), dim3(256), 0, (hipStream_t)stream, q, d, n);
+    return (int)hipGetLastError();
+}
+
+int launch_double_to_fixed(const double* d, unsigned long long* q, int64_t n, void* stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(double_to_fixed_kernel, dim3((unsigned)grid_for(n)), dim3(256), 0, (hipStream_t)stream, d, q, n);
+    return (int)hipGetLastError();
 }
 
 int launch_zero(void* ptr, int64_t bytes, void* stream) {

@@ -59,6 +59,7 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
+FLAG_DETERMINISTIC = 8
 
 _lib = None
 
@@ -171,7 +172,7 @@ class Plan:
 
     def __init__(self, positions, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0),
                  n_shells=0, r_max=0.0, origin_stride=1, device=0, timing=False, connected=False,
-                 key_table=True):
+                 key_table=True, deterministic=False):
         self._h = None
         pos = np.ascontiguousarray(positions, dtype=np.float32)
         self.n_sites = pos.shape[0]
@@ -181,7 +182,8 @@ class Plan:
         self.bins = bin_spec(kind, cells, n_shells, r_max)
         self.corr = corr_spec(n_origins, n_lags, precision, origin_stride,
                               flags=(FLAG_TIMING if timing else 0) | (FLAG_CONNECTED if connected else 0)
-                              | (0 if key_table else FLAG_NO_KEY_TABLE))
+                              | (0 if key_table else FLAG_NO_KEY_TABLE)
+                              | (FLAG_DETERMINISTIC if deterministic else 0))
         self.device = int(device)
         h = ctypes.c_void_p()
         _check(lib().sdc_plan_create(_np_ptr(pos), self.n_sites, ctypes.byref(self.bins),

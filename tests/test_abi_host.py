@@ -88,7 +88,7 @@ def test_validation_codes():
         (sdc.corr_spec(8, 0), good_b),
         (sdc.corr_spec(8, 16, origin_stride=0), good_b),
         (sdc.corr_spec(8, 16, precision=7), good_b),
-        (sdc.corr_spec(8, 16, flags=8), good_b),
+        (sdc.corr_spec(8, 16, flags=16), good_b),
         (good_c, sdc.bin_spec(9, (4, 4, 4))),
         (good_c, sdc.bin_spec(sdc.BINS_SC, (4, 4, 5))),       # wrong site count
         (good_c, sdc.bin_spec(sdc.BINS_RADIAL, n_shells=0, r_max=1.0)),

@@ -363,3 +363,49 @@ def test_structure_factor_matches_oracle(torch_dev, S, orc, prec, lat):
     with pytest.raises(S.SdcError):
         with S.Plan(inputs.ball_positions(64, 2.0, 1), S.BINS_RADIAL, 4, 4, prec, n_shells=8, r_max=4.0) as pr:
             pr.structure_factor(ms)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_deterministic_mode_bit_identical(torch_dev, S, orc, prec):
+    """SDC_FLAG_DETERMINISTIC: fixed-point sums make two runs (and a batch
+    run) bit-identical, and the result stays within the bar of the oracle."""
+    _say(f"deterministic mode {prec}")
+    cases = [
+        (S.BINS_SC, orc.SC, inputs.sc_positions((9, 10, 8)), dict(cells=(9, 10, 8))),
+        (S.BINS_BCC, orc.BCC, inputs.bcc_positions((5, 4, 6)), dict(cells=(5, 4, 6))),
+        (S.BINS_RADIAL, orc.RADIAL, inputs.ball_positions(600, 5.0, 4), dict(n_shells=128, r_max=10.0)),
+    ]
+    n_o, n_L = 24, 20
+    for kind, okind, pos, kw in cases:
+        fr = inputs.random_unit_frames(n_o + n_L - 1, pos.shape[0], seed=44)
+        d = torch_dev.from_numpy(fr).cuda()
+        runs = []
+        for _ in range(2):
+            with S.Plan(pos, kind, n_o, n_L, prec, deterministic=True, **kw) as p:
+                p.accumulate(d)
+                out = p.finalize()
+                runs.append((p.raw(), out))
+        (H0, no0, sf0, ms0), out0 = runs[0]
+        (H1, no1, sf1, ms1), out1 = runs[1]
+        np.testing.assert_array_equal(H0, H1)
+        np.testing.assert_array_equal(sf0, sf1)
+        np.testing.assert_array_equal(out0["C"], out1["C"])
+        np.testing.assert_array_equal(out0["Sself"], out1["Sself"])
+        Hr, cr = orc.binned_corr(pos, fr, okind, n_o, np.arange(n_L), **kw)
+        C, *_ = orc.finalize(Hr, cr, pos.shape[0], float(n_o), orc.self_corr(fr, n_o, np.arange(n_L)))
+        e = _normwise(out0["C"], C)
+        print(f"  kind {kind}: normwise error {e:.3e}", flush=True)
+        assert e <= _tol_random(prec, cr, n_o)
+        # one partial per site is rounded to 2^-20: at most N * 2^-21 in all
+        np.testing.assert_allclose(sf0, orc.self_corr(fr, n_o, np.arange(n_L)), rtol=1e-12,
+                                   atol=pos.shape[0] * 2.0 ** -21)
+    # a batch in deterministic mode gives the same bits as the single plan
+    pos, kw = cases[0][2], cases[0][3]
+    fr = inputs.random_unit_frames(n_o + n_L - 1, pos.shape[0], seed=44)
+    d = torch_dev.from_numpy(fr).cuda()
+    with S.Plan(pos, S.BINS_SC, n_o, n_L, prec, deterministic=True, **kw) as a, \
+            S.Plan(pos, S.BINS_SC, n_o, n_L, prec, deterministic=True, **kw) as b:
+        a.accumulate(d)
+        with S.Batch([b]) as bt:
+            bt.accumulate([d])
+        np.testing.assert_array_equal(a.raw()[0], b.raw()[0])

@@ -409,3 +409,46 @@ def test_deterministic_mode_bit_identical(torch_dev, S, orc, prec):
         with S.Batch([b]) as bt:
             bt.accumulate([d])
         np.testing.assert_array_equal(a.raw()[0], b.raw()[0])
+
+
+def test_edge_cases(torch_dev, S, orc):
+    """Single site, single origin, single lag, and the options combined."""
+    _say("edge cases")
+    # one site, one origin, one lag: C(0, 0) = |S|^2 = 1 for an axis spin
+    for kind, pos, kw in [(S.BINS_SC, inputs.sc_positions((1, 1, 1)), dict(cells=(1, 1, 1))),
+                          (S.BINS_RADIAL, np.zeros((1, 3), np.float32), dict(n_shells=4, r_max=1.0))]:
+        fr = inputs.axis_frames(1, 1, seed=3)
+        with S.Plan(pos, kind, 1, 1, "split_bf16", **kw) as p:
+            p.accumulate(torch_dev.from_numpy(fr).cuda())
+            out = p.finalize()
+        assert out["counts"][0] == 1 and out["C"][0, 0] == 1.0 and out["Cself"][0] == 1.0
+    # one origin, several lags, ragged box
+    L = (3, 1, 5)
+    pos = inputs.sc_positions(L)
+    fr = inputs.random_unit_frames(4, pos.shape[0], seed=6)
+    with S.Plan(pos, S.BINS_SC, 1, 4, "fp32", cells=L) as p:
+        p.accumulate(torch_dev.from_numpy(fr).cuda())
+        out = p.finalize()
+    Hr, cr = orc.binned_corr(pos, fr, orc.SC, 1, np.arange(4), cells=L)
+    C, *_ = orc.finalize(Hr, cr, pos.shape[0], 1.0, orc.self_corr(fr, 1, np.arange(4)))
+    assert _normwise(out["C"], C) <= 1e-6
+    # connected + deterministic + BF16x3 + origin stride 2, single plan and batch
+    L = (4, 3, 5)
+    pos = inputs.bcc_positions(L)
+    n_o, n_L, s = 9, 7, 2
+    fr = inputs.random_unit_frames((n_o - 1) * s + n_L, pos.shape[0], seed=8).astype(np.float64)
+    fr[:, :, 0] += 0.5
+    fr = fr.astype(np.float32)
+    d = torch_dev.from_numpy(fr).cuda()
+    Hr, cr = orc.binned_corr(pos, fr, orc.BCC, n_o, np.arange(n_L), stride=s, cells=L, connected=True)
+    sfr = orc.self_corr(fr, n_o, np.arange(n_L), stride=s, connected=True)
+    C, *_ = orc.finalize(Hr, cr, pos.shape[0], float(n_o), sfr)
+    kw = dict(cells=L, origin_stride=s, connected=True, deterministic=True)
+    with S.Plan(pos, S.BINS_BCC, n_o, n_L, "bf16x3", **kw) as a, \
+            S.Plan(pos, S.BINS_BCC, n_o, n_L, "bf16x3", **kw) as b:
+        a.accumulate(d)
+        with S.Batch([b]) as bt:
+            bt.accumulate([d])
+        oa, ob = a.finalize(), b.finalize()
+        np.testing.assert_array_equal(oa["C"], ob["C"])
+        assert _normwise(oa["C"], C) <= 1e-6

@@ -452,3 +452,26 @@ def test_edge_cases(torch_dev, S, orc):
         oa, ob = a.finalize(), b.finalize()
         np.testing.assert_array_equal(oa["C"], ob["C"])
         assert _normwise(oa["C"], C) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_square_lattice_2d(torch_dev, S, orc, prec):
+    """The paper's geometry, a 2D square lattice, is the sc kind with one cell
+    along z; an RK4 trajectory of it (the +-z bonds close on the site itself
+    and drop out of the precession) against the oracle."""
+    _say(f"2D square lattice {prec}")
+    L = (24, 18, 1)
+    pos = inputs.sc_positions(L)
+    n_o, n_L = 20, 16
+    fr = torch_dev.empty((n_o + n_L - 1, pos.shape[0], 3), dtype=torch_dev.float32, device="cuda")
+    S.traj_generate(pos, S.BINS_SC, fr, cells=L, J=-1.0, dt=0.02, init=S.INIT_PERTURBED_Z, sigma=0.4, seed=7)
+    with S.Plan(pos, S.BINS_SC, n_o, n_L, prec, cells=L) as p:
+        p.accumulate(fr)
+        out = p.finalize()
+    frh = fr.cpu().numpy()
+    Hr, cr = orc.binned_corr(pos, frh, orc.SC, n_o, np.arange(n_L), cells=L)
+    np.testing.assert_array_equal(out["counts"], cr)
+    C, *_ = orc.finalize(Hr, cr, pos.shape[0], float(n_o), orc.self_corr(frh, n_o, np.arange(n_L)))
+    e = _normwise(out["C"], C)
+    print(f"  normwise error {e:.3e}", flush=True)
+    assert e <= TOL[prec]

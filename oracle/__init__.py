@@ -14,7 +14,10 @@ Each function states the paper passage it follows (arXiv 2308.07487):
                        with ``connected=True`` the second term of Eq. (4), the
                        product of the per-site averages over the origins
                        (``mean_product``), is subtracted.
-- ``structure_factor`` Eq. (3), the double sum over site pairs written out.
+- ``structure_factor_q`` Eq. (3), the double sum over site pairs written out,
+                       at any wave vector (``structure_factor``: the ones
+                       commensurate with a periodic box); ``connected`` takes
+                       Eq. (4) with its second term.
 - ``finalize``         per-bin normalisation, site sum (Sec. 1: summing the
                        correlation over all sites) and the windowed time
                        transform of Sec. 2.2.
@@ -216,24 +219,36 @@ def self_corr(frames, n_origins, lags, stride=1, connected=False):
 
 
 def structure_factor(pos, frames, n_origins, lags, m, cells, stride=1):
-    """Eq. (3) written out: for q_a = 2 pi m_a / L_a,
-    S(q, t) = (1 / (N n_o)) sum_o sum_i sum_j exp(-i q.(r_j - r_i)) S_i(o s) . S_j(o s + t),
-    the double sum over all ordered site pairs with the actual positions
-    (numpy, FP64; the per-origin pair matrix is a matrix product).
+    """Eq. (3) at the wave vectors commensurate with a periodic box,
+    q_a = 2 pi m_a / L_a (``structure_factor_q`` with those q).
     Returns complex128 [n_q][n_lags]."""
+    m = np.atleast_2d(np.asarray(m, dtype=np.float64))
+    L = np.asarray(cells, dtype=np.float64)
+    return structure_factor_q(pos, frames, n_origins, lags, 2.0 * np.pi * m / L, stride=stride)
+
+
+def structure_factor_q(pos, frames, n_origins, lags, q, stride=1, connected=False):
+    """Eq. (3) written out at arbitrary wave vectors q (rows of [n_q][3]):
+    S(q, t) = (1 / (N n_o)) sum_o sum_i sum_j exp(-i q.(r_j - r_i)) S_i(o s) . S_j(o s + t),
+    the double sum over all ordered site pairs with the actual positions r
+    (no periodic image), site j at the later time.  ``connected`` subtracts
+    the second term of Eq. (4): n_o <S_i(t0)> . <S_j(t0 + t)> per pair, <.>
+    the average over the origins t0 = o s.  numpy, FP64; the per-origin pair
+    matrix is a matrix product.  Returns complex128 [n_q][n_lags]."""
     pos = np.asarray(pos, dtype=np.float64)
     f = np.asarray(frames, dtype=np.float64)
     n = pos.shape[0]
-    m = np.atleast_2d(np.asarray(m, dtype=np.float64))
-    L = np.asarray(cells, dtype=np.float64)
-    out = np.zeros((m.shape[0], len(lags)), dtype=np.complex128)
+    q = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    out = np.zeros((q.shape[0], len(lags)), dtype=np.complex128)
+    org = np.arange(n_origins) * stride
     for li, t in enumerate(lags):
         G = np.zeros((n, n))
-        for o in range(n_origins):
-            G += f[o * stride] @ f[o * stride + t].T  # G[i, j] = S_i(o s) . S_j(o s + t)
-        for qi in range(m.shape[0]):
-            q = 2.0 * np.pi * m[qi] / L
-            phase = np.exp(-1j * (pos @ q))          # exp(-i q.r)
+        for o in org:
+            G += f[o] @ f[o + t].T  # G[i, j] = S_i(o s) . S_j(o s + t)
+        if connected:
+            G -= n_origins * (f[org].mean(axis=0) @ f[org + t].mean(axis=0).T)
+        for qi in range(q.shape[0]):
+            phase = np.exp(-1j * (pos @ q[qi]))          # exp(-i q.r)
             P = np.conj(phase)[:, None] * phase[None, :]  # exp(-i q.(r_j - r_i))
             out[qi, li] = np.sum(P * G) / (n * n_origins)
     return out

@@ -605,3 +605,78 @@ def test_structure_factor_matches_bins(orc):
         q = 2 * np.pi * mq / np.array(L)
         ph = np.exp(-1j * (d @ q))
         np.testing.assert_allclose((H @ ph) / (n * n_o), S[qi], rtol=1e-12, atol=1e-12)
+
+
+def _dsum(pos, p):
+    """D(p) = sum_j exp(i p.r_j), one sum over the sites (FP64)."""
+    return np.sum(np.exp(1j * (np.asarray(pos, dtype=np.float64) @ np.asarray(p, dtype=np.float64))))
+
+
+def test_structure_factor_q_spin_wave_any_points(orc):
+    """Eq. (3) at arbitrary q on points without any lattice: for a spin wave
+    S_i = (sin th cos phi_i, sin th sin phi_i, cos th), phi_i = k.r_i - w t,
+    the pair sum collapses to single site sums D(p) = sum_j exp(i p.r_j):
+    S(q, t) = [ sin^2 th (|D(k - q)|^2 e^{-i w t} + |D(-k - q)|^2 e^{i w t}) / 2
+               + cos^2 th |D(-q)|^2 ] / N.
+    A conjugate on the wrong factor, a flipped time direction or a dropped
+    component changes it by O(N)."""
+    pos = inputs.ball_positions(300, 4.0, seed=31)
+    n = pos.shape[0]
+    k = np.array([0.83, -0.41, 0.27])
+    theta, omega, dt = 0.9, 1.3, 0.1
+    n_o, lags = 5, [0, 1, 3]
+    fr = inputs.spiral_frames(pos, k, theta, omega, n_o + max(lags), dt)
+    qs = np.array([k, -k, [0.0, 0.0, 0.0], [0.3, 0.5, -0.7], 0.5 * k])
+    S = orc.structure_factor_q(pos, fr, n_o, lags, qs)
+    tau = dt * np.array(lags)
+    for qi, q in enumerate(qs):
+        a, b, c = _dsum(pos, k - q), _dsum(pos, -k - q), _dsum(pos, -q)
+        ref = (0.5 * np.sin(theta) ** 2 * (abs(a) ** 2 * np.exp(-1j * omega * tau)
+                                           + abs(b) ** 2 * np.exp(1j * omega * tau))
+               + np.cos(theta) ** 2 * abs(c) ** 2) / n
+        np.testing.assert_allclose(S[qi], ref, rtol=0, atol=2e-6 * n)
+
+
+def test_structure_factor_q_invariants(orc):
+    """Shifting every position by one vector leaves S(q, t) unchanged (only
+    differences r_j - r_i enter); S(-q, t) = conj S(q, t) for real spins; at
+    q = 0 it is the magnetisation product sum_o M(o).M(o + t) / (N n_o)."""
+    pos = inputs.ball_positions(120, 3.0, seed=32).astype(np.float64)
+    n = pos.shape[0]
+    fr = inputs.random_unit_frames(9, n, seed=33)
+    n_o, lags = 4, [0, 2, 5]
+    qs = np.array([[0.7, -1.1, 0.4], [2.3, 0.2, -0.9]])
+    S = orc.structure_factor_q(pos, fr, n_o, lags, qs)
+    Ssh = orc.structure_factor_q(pos + np.array([3.7, -12.25, 0.5]), fr, n_o, lags, qs)
+    np.testing.assert_allclose(Ssh, S, rtol=0, atol=1e-11)
+    Sneg = orc.structure_factor_q(pos, fr, n_o, lags, -qs)
+    np.testing.assert_allclose(Sneg, np.conj(S), rtol=0, atol=1e-11)
+    assert np.max(np.abs(S.imag)) > 1e-3  # not trivially real
+    S0 = orc.structure_factor_q(pos, fr, n_o, lags, [[0.0, 0.0, 0.0]])[0]
+    M = fr.astype(np.float64).sum(axis=1)
+    ref = [sum(M[o] @ M[o + t] for o in range(n_o)) / (n * n_o) for t in lags]
+    np.testing.assert_allclose(S0, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_structure_factor_q_connected(orc):
+    """Connected form: static spins give zero (each equals its own average);
+    on a periodic lattice at commensurate q it equals the connected bins
+    (Eq. (4) with its second term, from the C oracle) weighted by
+    exp(-i q.d_b)."""
+    pos = inputs.ball_positions(64, 2.0, seed=34)
+    fr = inputs.static_frames(6, 64, (0.3, -0.5, 0.8))
+    S = orc.structure_factor_q(pos, fr, 3, [0, 2], [[0.4, 0.1, -0.2], [0.0, 0.0, 0.0]], connected=True)
+    assert np.max(np.abs(S)) < 1e-12
+    L = (4, 3, 2)
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    fr = inputs.random_unit_frames(10, n, seed=35)
+    n_o, lags = 5, [0, 1, 4]
+    ms = np.array([[1, 0, 1], [2, 1, 0], [0, 0, 0]])
+    S = orc.structure_factor_q(pos, fr, n_o, lags, 2 * np.pi * ms / np.array(L), connected=True)
+    H, _ = orc.binned_corr(pos, fr, orc.SC, n_o, lags, cells=L, connected=True)
+    b = np.arange(n)
+    d = np.stack([b // (L[1] * L[2]), (b // L[2]) % L[1], b % L[2]], axis=1).astype(np.float64)
+    for qi, mq in enumerate(ms):
+        ph = np.exp(-1j * (d @ (2 * np.pi * mq / np.array(L))))
+        np.testing.assert_allclose((H @ ph) / (n * n_o), S[qi], rtol=0, atol=1e-12)

@@ -293,6 +293,79 @@ sdc_status sdc_batch_info(const sdc_batch* batch, int64_t* n_tasks, int32_t* gri
  * no-op. */
 sdc_status sdc_batch_destroy(sdc_batch* batch);
 
+/* ---------------------------------------------------------------------- */
+/* q-resolved dynamic structure factor at arbitrary wave vectors          */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t n_origins;     /* time origins per accumulate call, [1, 4096]    */
+    int32_t n_lags;        /* lags 0..n_lags-1 in frames, [1, 1024]           */
+    int32_t origin_stride; /* frames between origins s, [1, 64]               */
+    int32_t flags;         /* SDC_FLAG_TIMING | SDC_FLAG_CONNECTED            */
+} sdc_sq_spec;
+
+typedef struct sdc_sq sdc_sq;
+
+/*
+ * Create an accumulator of Eq. (3) at a list of arbitrary wave vectors for
+ * any point set (periodic or not; no binning, no periodic image):
+ *     S(q, t) = (1 / (N n_org)) sum_o sum_{i,j} exp(-i q.(r_j - r_i))
+ *               S_i(o s) . S_j(o s + t),
+ * site j at the later time, r the given positions.  This is the quantity
+ * the paper's fused kernel evaluates with the on-the-fly Q of Eq. (6)
+ * (Sec. 3.4); here the phase is split per site, exp(-i q.(r_j - r_i)) =
+ * conj(e_i) e_j, so each accumulate is one FP64 matrix-core contraction of
+ * the [n_q x N] phases with the [N x 3T] spins followed by a correlation
+ * over the origins, O(n_q N T) instead of O(n_q N^2 T) work.  Everything is
+ * FP64 after the fp32 inputs (phases q.r and sin/cos in FP64).
+ *  positions_host : [n_sites][3] fp32, host, copied; finite.
+ *  q_host         : [n_q][3] FP64 wave vectors (radians per unit length),
+ *                   host, copied; finite.  1 <= n_q <= 65536.
+ *  spec           : origins, lags, stride as in sdc_corr_spec; flags
+ *                   SDC_FLAG_CONNECTED subtracts the second term of Eq. (4)
+ *                   per pair (the product of the per-site averages over each
+ *                   call's origins), SDC_FLAG_TIMING records HIP events.
+ *  device         : HIP device ordinal.
+ * Allocates all device memory the accumulator needs (the per-site-range
+ * partial transforms, at most 1 GiB, and the [n_q][3T] transform).
+ * Errors: INVALID_ARG, OOM, NO_DEVICE, HIP.
+ */
+sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const double* q_host, int32_t n_q,
+                         const sdc_sq_spec* spec, int device, sdc_sq** out);
+
+/*
+ * Add one trajectory: spins_dev [n_frames][n_sites][3] fp32 device memory
+ * (site order of positions_host), n_frames >= (n_origins - 1) s + n_lags,
+ * read-only until the stream reaches this work.  Queued on the stream with
+ * no allocation and no host synchronisation; deterministic (no atomics: the
+ * partial transforms of the site ranges are summed in a fixed order).
+ * Calls on one accumulator must not overlap in time.
+ * Errors: INVALID_ARG, STATE, HIP.
+ */
+sdc_status sdc_sq_accumulate(sdc_sq* sq, const float* spins_dev, int64_t n_frames, void* stream);
+
+/*
+ * Sqt_host : [n_q][n_lags][2] (re, im) of S(q, t) over all accumulated
+ *            origins, or NULL.
+ * Sqw_host : [n_q][n_lags][2] windowed time transform
+ *            sum_t w_t S(q, t) exp(-2 pi i k t / n_lags),
+ *            w_t = (1 + cos(pi t / n_lags)) / 2, or NULL.
+ * Synchronises the stream; does not reset.  Errors: INVALID_ARG, STATE, HIP.
+ */
+sdc_status sdc_sq_finalize(sdc_sq* sq, double* Sqt_host, double* Sqw_host, void* stream);
+
+/* Durations (milliseconds) of the most recent accumulate of an accumulator
+ * created with SDC_FLAG_TIMING: ms[0] the phase contraction (with the sum
+ * of its site ranges), ms[1] the correlation over origins.  Waits for those
+ * events.  Errors: INVALID_ARG, STATE, HIP. */
+sdc_status sdc_sq_timings(sdc_sq* sq, double* ms);
+
+/* Zero the accumulated sums and origin total.  Queued on the stream. */
+sdc_status sdc_sq_reset(sdc_sq* sq, void* stream);
+
+/* Free the accumulator (waits for the device).  NULL is a no-op. */
+sdc_status sdc_sq_destroy(sdc_sq* sq);
+
 /* Static description of a status code. */
 const char* sdc_status_string(sdc_status s);
 

@@ -996,3 +996,230 @@ sdc_status sdc_batch_destroy(sdc_batch* b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// q-resolved S(q, t) at arbitrary wave vectors
+// ---------------------------------------------------------------------------
+
+// Largest memory of the per-site-range partial transforms.
+constexpr size_t kMaxSqPartBytes = (size_t)1 << 30;
+
+struct sdc_sq {
+    int device = 0;
+    sdc_sq_spec spec{};
+    int64_t n = 0;
+    int n_q = 0;
+    int t_used = 0;
+    int n_split = 1;
+    int64_t sites_per_split = 0;
+    std::vector<void*> owned;
+    float* d_pos = nullptr;
+    double* d_q = nullptr;
+    double* d_part = nullptr;  // [n_split][n_q][2][3 t_used]
+    double* d_F = nullptr;     // [n_q][t_used][3][2]
+    double* d_raw = nullptr;   // [n_q][n_lags][2]
+    double* d_norg = nullptr;  // [1]
+    double* d_out = nullptr;   // [2][n_q][n_lags][2]: S(q, t), S(q, w)
+    bool failed = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
+
+    ~sdc_sq() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+sdc_status sq_usable(const sdc_sq* q) {
+    if (!q) return set_err(SDC_ERR_INVALID_ARG, "null accumulator");
+    if (q->failed) return set_err(SDC_ERR_STATE, "accumulator is unusable after an earlier device failure");
+    return SDC_OK;
+}
+
+}  // namespace
+
+sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const double* q_host, int32_t n_q,
+                         const sdc_sq_spec* spec, int device, sdc_sq** out) {
+    g_err.clear();
+    if (!out) return set_err(SDC_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (!positions_host || !q_host || !spec) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    if (n_sites < 1 || n_sites > ((int64_t)1 << 31)) return set_err(SDC_ERR_INVALID_ARG, "n_sites must be in [1, 2^31]");
+    if (n_q < 1 || n_q > 65536) return set_err(SDC_ERR_INVALID_ARG, "n_q must be in [1, 65536]");
+    if (spec->n_origins < 1 || spec->n_origins > 4096)
+        return set_err(SDC_ERR_INVALID_ARG, "n_origins must be in [1, 4096]");
+    if (spec->n_lags < 1 || spec->n_lags > 1024) return set_err(SDC_ERR_INVALID_ARG, "n_lags must be in [1, 1024]");
+    if (spec->origin_stride < 1 || spec->origin_stride > 64)
+        return set_err(SDC_ERR_INVALID_ARG, "origin_stride must be in [1, 64]");
+    if ((spec->flags & ~(SDC_FLAG_TIMING | SDC_FLAG_CONNECTED)) != 0)
+        return set_err(SDC_ERR_INVALID_ARG, "unknown flags (only TIMING and CONNECTED apply)");
+    for (int64_t x = 0; x < 3 * n_sites; ++x)
+        if (!std::isfinite(positions_host[x])) return set_err(SDC_ERR_INVALID_ARG, "non-finite position");
+    for (int64_t x = 0; x < 3 * (int64_t)n_q; ++x)
+        if (!std::isfinite(q_host[x])) return set_err(SDC_ERR_INVALID_ARG, "non-finite wave vector");
+    sdc_status s = use_device(device);
+    if (s != SDC_OK) return s;
+    sdc_sq* q = nullptr;
+    try {
+        q = new sdc_sq();
+    } catch (const std::bad_alloc&) {
+        return set_err(SDC_ERR_OOM, "host allocation failed");
+    }
+    q->device = device;
+    q->spec = *spec;
+    q->n = n_sites;
+    q->n_q = n_q;
+    q->t_used = (spec->n_origins - 1) * spec->origin_stride + spec->n_lags;
+    const int64_t n_cols = 3 * (int64_t)q->t_used;
+    // Site ranges: enough workgroups to fill the chip (about 2048), at least
+    // four staged chunks per range, partials within kMaxSqPartBytes.
+    const int64_t chunk = sdc::sq_site_chunk();
+    const int64_t tiles = sdc::sq_tiles_per_split(n_q, q->t_used);
+    const size_t per_split = (size_t)n_q * 2 * n_cols * sizeof(double);
+    int64_t split = (2048 + tiles - 1) / tiles;
+    split = std::min<int64_t>(split, std::max<int64_t>(1, n_sites / (4 * chunk)));
+    split = std::min<int64_t>(split, std::max<int64_t>(1, (int64_t)(kMaxSqPartBytes / per_split)));
+    split = std::max<int64_t>(1, std::min<int64_t>(split, 65535));
+    int64_t sps = (n_sites + split - 1) / split;
+    sps = (sps + chunk - 1) / chunk * chunk;
+    q->sites_per_split = sps;
+    q->n_split = (int)((n_sites + sps - 1) / sps);
+    const size_t out_n = (size_t)n_q * spec->n_lags * 2;
+#define SQ_TRY(x)               \
+    do {                        \
+        sdc_status s_ = (x);    \
+        if (s_ != SDC_OK) {     \
+            delete q;           \
+            return s_;          \
+        }                       \
+    } while (0)
+    SQ_TRY(dalloc(&q->d_pos, (size_t)3 * n_sites, &q->owned));
+    SQ_TRY(dalloc(&q->d_q, (size_t)3 * n_q, &q->owned));
+    SQ_TRY(dalloc(&q->d_part, (size_t)q->n_split * n_q * 2 * n_cols, &q->owned));
+    SQ_TRY(dalloc(&q->d_F, (size_t)n_q * 2 * n_cols, &q->owned));
+    SQ_TRY(dalloc(&q->d_raw, out_n, &q->owned));
+    SQ_TRY(dalloc(&q->d_norg, 1, &q->owned));
+    SQ_TRY(dalloc(&q->d_out, 2 * out_n, &q->owned));
+#undef SQ_TRY
+    hipError_t e = hipMemcpy(q->d_pos, positions_host, (size_t)3 * n_sites * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->d_q, q_host, (size_t)3 * n_q * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = (hipError_t)sdc::launch_zero(q->d_raw, (int64_t)out_n * 8, nullptr);
+    if (e == hipSuccess) e = (hipError_t)sdc::launch_zero(q->d_norg, 8, nullptr);
+    if (e == hipSuccess && (spec->flags & SDC_FLAG_TIMING))
+        for (hipEvent_t& ev : q->ev)
+            if (e == hipSuccess) e = hipEventCreate(&ev);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete q;
+        return hip_err((int)e, "accumulator set-up");
+    }
+    *out = q;
+    return SDC_OK;
+}
+
+sdc_status sdc_sq_accumulate(sdc_sq* q, const float* spins_dev, int64_t n_frames, void* stream) {
+    g_err.clear();
+    sdc_status s = sq_usable(q);
+    if (s != SDC_OK) return s;
+    if (!spins_dev) return set_err(SDC_ERR_INVALID_ARG, "null spins");
+    if (n_frames < q->t_used)
+        return set_err(SDC_ERR_INVALID_ARG, "n_frames must be >= (n_origins - 1) * stride + n_lags");
+    SDC_HIP(select_device(q->device), "hipSetDevice");
+    const bool timing = (q->spec.flags & SDC_FLAG_TIMING) != 0;
+    hipStream_t hs = (hipStream_t)stream;
+    sdc::SqTransformArgs ta{};
+    ta.frames = spins_dev;
+    ta.pos = q->d_pos;
+    ta.q = q->d_q;
+    ta.n = q->n;
+    ta.n_q = q->n_q;
+    ta.n_frames_used = q->t_used;
+    ta.n_split = q->n_split;
+    ta.sites_per_split = q->sites_per_split;
+    ta.part = q->d_part;
+    sdc::SqCorrArgs ca{};
+    ca.F = q->d_F;
+    ca.n_q = q->n_q;
+    ca.n_cols = 3 * (int64_t)q->t_used;
+    ca.n_origins = q->spec.n_origins;
+    ca.stride = q->spec.origin_stride;
+    ca.n_lags = q->spec.n_lags;
+    ca.connected = (q->spec.flags & SDC_FLAG_CONNECTED) ? 1 : 0;
+    ca.raw = q->d_raw;
+    ca.n_org = q->d_norg;
+    if (timing) SDC_HIP(hipEventRecord(q->ev[0], hs), "hipEventRecord");
+    int e = sdc::launch_sq_transform(ta, q->d_F, stream);
+    if (e == 0 && timing) e = (int)hipEventRecord(q->ev[1], hs);
+    if (e == 0) e = sdc::launch_sq_corr(ca, stream);
+    if (e == 0 && timing) e = (int)hipEventRecord(q->ev[2], hs);
+    if (e != 0) {
+        q->failed = true;
+        return hip_err(e, "structure factor kernels");
+    }
+    if (timing) q->timed = true;
+    return SDC_OK;
+}
+
+sdc_status sdc_sq_finalize(sdc_sq* q, double* Sqt_host, double* Sqw_host, void* stream) {
+    g_err.clear();
+    sdc_status s = sq_usable(q);
+    if (s != SDC_OK) return s;
+    if (!Sqt_host && !Sqw_host) return set_err(SDC_ERR_INVALID_ARG, "no output requested");
+    SDC_HIP(select_device(q->device), "hipSetDevice");
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t out_n = (size_t)q->n_q * q->spec.n_lags * 2;
+    int e = sdc::launch_sq_finalize(q->d_raw, q->d_norg, q->n, q->n_q, q->spec.n_lags, q->d_out, q->d_out + out_n,
+                                    stream);
+    if (e == 0 && Sqt_host)
+        e = (int)hipMemcpyAsync(Sqt_host, q->d_out, out_n * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == 0 && Sqw_host)
+        e = (int)hipMemcpyAsync(Sqw_host, q->d_out + out_n, out_n * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == 0) e = (int)hipStreamSynchronize(hs);
+    if (e != 0) {
+        q->failed = true;
+        return hip_err(e, "structure factor finalize (or earlier queued work)");
+    }
+    return SDC_OK;
+}
+
+sdc_status sdc_sq_timings(sdc_sq* q, double* ms) {
+    g_err.clear();
+    sdc_status s = sq_usable(q);
+    if (s != SDC_OK) return s;
+    if (!ms) return set_err(SDC_ERR_INVALID_ARG, "null output");
+    if (!(q->spec.flags & SDC_FLAG_TIMING) || !q->timed)
+        return set_err(SDC_ERR_STATE, "no timed accumulate (create with SDC_FLAG_TIMING)");
+    SDC_HIP(hipEventSynchronize(q->ev[2]), "hipEventSynchronize");
+    for (int k = 0; k < 2; ++k) {
+        float t = 0.0f;
+        SDC_HIP(hipEventElapsedTime(&t, q->ev[k], q->ev[k + 1]), "hipEventElapsedTime");
+        ms[k] = t;
+    }
+    return SDC_OK;
+}
+
+sdc_status sdc_sq_reset(sdc_sq* q, void* stream) {
+    g_err.clear();
+    sdc_status s = sq_usable(q);
+    if (s != SDC_OK) return s;
+    SDC_HIP(select_device(q->device), "hipSetDevice");
+    int e = sdc::launch_zero(q->d_raw, (int64_t)q->n_q * q->spec.n_lags * 16, stream);
+    if (e == 0) e = sdc::launch_zero(q->d_norg, 8, stream);
+    if (e != 0) {
+        q->failed = true;
+        return hip_err(e, "reset");
+    }
+    return SDC_OK;
+}
+
+sdc_status sdc_sq_destroy(sdc_sq* q) {
+    g_err.clear();
+    if (!q) return SDC_OK;
+    (void)hipSetDevice(q->device);
+    (void)hipDeviceSynchronize();
+    delete q;
+    return SDC_OK;
+}

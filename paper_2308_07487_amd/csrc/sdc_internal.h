@@ -268,6 +268,39 @@ struct SqtArgs {
     double* sqw;           // [n_q][n_lags][2]
 };
 int launch_sqt(const SqtArgs& a, void* stream);
+// Windowed time transform of S(q, t) for every q (the window of the site sums):
+// sqw[q][k] = sum_t w_t sqt[q][t] exp(-2 pi i k t / n_lags), (re, im) pairs.
+int launch_sqw(const double* sqt, double* sqw, int n_q, int n_lags, void* stream);
+
+// q-resolved S(q, t) of Eq. (3) at arbitrary wave vectors (sdc_sq.hip).
+struct SqTransformArgs {
+    const float* frames;      // [>= n_frames_used][n][3] fp32, caller's site order
+    const float* pos;         // [n][3] fp32
+    const double* q;          // [n_q][3]
+    int64_t n;
+    int n_q;
+    int n_frames_used;        // (n_origins - 1) * stride + n_lags
+    int n_split;              // site ranges, one partial transform each
+    int64_t sites_per_split;
+    double* part;             // [n_split][n_q][2][3 n_frames_used]
+};
+struct SqCorrArgs {
+    const double* F;          // [n_q][n_frames_used][3][2]
+    int n_q;
+    int64_t n_cols;           // 3 n_frames_used
+    int n_origins, stride, n_lags;
+    int connected;
+    double* raw;              // [n_q][n_lags][2], accumulated
+    double* n_org;            // [1] origins accumulated
+};
+// Workgroups of the transform per site range, and the sites one workgroup
+// stages per step (site ranges are multiples of it).
+int64_t sq_tiles_per_split(int n_q, int n_frames_used);
+int sq_site_chunk();
+int launch_sq_transform(const SqTransformArgs& a, double* F, void* stream);
+int launch_sq_corr(const SqCorrArgs& a, void* stream);
+int launch_sq_finalize(const double* raw, const double* n_org, int64_t n_sites, int n_q, int n_lags, double* sqt,
+                       double* sqw, void* stream);
 
 int launch_zero(void* ptr, int64_t bytes, void* stream);
 

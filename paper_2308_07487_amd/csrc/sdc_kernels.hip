@@ -1134,12 +1134,11 @@ __global__ __launch_bounds__(256) void sqt_kernel(SqtArgs a) {
 }
 
 // Windowed DFT over the lags of each q (same window as the site sums).
-__global__ void sqw_kernel(SqtArgs a) {
+__global__ void sqw_kernel(const double* __restrict__ sqt, double* __restrict__ sqw, int m) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int qi = blockIdx.y;
-    const int m = a.n_lags;
     if (k >= m) return;
-    const double* x = a.sqt + (int64_t)qi * m * 2;
+    const double* x = sqt + (int64_t)qi * m * 2;
     double re = 0.0, im = 0.0;
     for (int t = 0; t < m; ++t) {
         const double w = 0.5 * (1.0 + cospi((double)t / (double)m));
@@ -1150,16 +1149,22 @@ __global__ void sqw_kernel(SqtArgs a) {
         re += w * (x[2 * t] * cs - x[2 * t + 1] * sn);
         im += w * (x[2 * t] * sn + x[2 * t + 1] * cs);
     }
-    a.sqw[((int64_t)qi * m + k) * 2] = re;
-    a.sqw[((int64_t)qi * m + k) * 2 + 1] = im;
+    sqw[((int64_t)qi * m + k) * 2] = re;
+    sqw[((int64_t)qi * m + k) * 2 + 1] = im;
+}
+
+int launch_sqw(const double* sqt, double* sqw, int n_q, int n_lags, void* stream) {
+    if (n_q == 0) return 0;
+    hipLaunchKernelGGL(sqw_kernel, dim3((unsigned)((n_lags + 63) / 64), (unsigned)n_q), dim3(64), 0,
+                       (hipStream_t)stream, sqt, sqw, n_lags);
+    return (int)hipGetLastError();
 }
 
 int launch_sqt(const SqtArgs& a, void* stream) {
     if (a.n_q == 0) return 0;
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(sqt_kernel, dim3((unsigned)a.n_q, (unsigned)a.n_lags), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sqw_kernel, dim3((unsigned)((a.n_lags + 63) / 64), (unsigned)a.n_q), dim3(64), 0, s, a);
-    return (int)hipGetLastError();
+    hipLaunchKernelGGL(sqt_kernel, dim3((unsigned)a.n_q, (unsigned)a.n_lags), dim3(256), 0, (hipStream_t)stream, a);
+    const int e = (int)hipGetLastError();
+    return e != 0 ? e : launch_sqw(a.sqt, a.sqw, a.n_q, a.n_lags, stream);
 }
 
 int launch_finalize(const FinalArgs& a, void* stream) {

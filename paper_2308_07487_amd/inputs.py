@@ -15,6 +15,8 @@ Workload recipes (lattice constant 1, unit spins, fp32 xyz):
   that every product and every partial sum up to 2^24 units is exact in FP32.
 - ``static_frames``: every spin along one fixed axis in every frame.
 - ``spiral_frames``: a planted spin wave with a commensurate wave vector.
+- ``powder_wave_vectors``: wave vectors with random directions and a range
+  of magnitudes, for q-resolved spectra of samples without a lattice.
 - ``batch_samples``: the recipe of a batch of independent samples (lattice,
   box edge, origin and lag counts, seeds), as the paper's averages over many
   realizations of different lattices need.
@@ -116,3 +118,13 @@ def _dims(L):
     if np.isscalar(L):
         return (int(L),) * 3
     return tuple(int(x) for x in L)
+
+
+def powder_wave_vectors(n_q, q_min, q_max, seed):
+    """n_q wave vectors with directions uniform on the sphere and magnitudes
+    uniform in [q_min, q_max] (radians per unit length), for samples without
+    a reciprocal lattice."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n_q, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v * rng.uniform(q_min, q_max, size=(n_q, 1))

@@ -43,6 +43,11 @@ class CorrSpec(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class SqSpec(ctypes.Structure):
+    _fields_ = [("n_origins", ctypes.c_int32), ("n_lags", ctypes.c_int32),
+                ("origin_stride", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
 class TrajSpec(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("cells", ctypes.c_int32 * 3),
                 ("coupling", ctypes.c_int32), ("r_cut", ctypes.c_float), ("J", ctypes.c_double),
@@ -55,7 +60,8 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_plan_load_raw", "sdc_plan_timings", "sdc_plan_reset", "sdc_plan_destroy",
            "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate",
            "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_timings", "sdc_batch_info",
-           "sdc_batch_destroy", "sdc_plan_structure_factor")
+           "sdc_batch_destroy", "sdc_plan_structure_factor", "sdc_sq_create", "sdc_sq_accumulate",
+           "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -95,6 +101,12 @@ def lib():
         L.sdc_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.sdc_batch_destroy.argtypes = [P]
         L.sdc_plan_structure_factor.argtypes = [P, P, i32, P, P, P]
+        L.sdc_sq_create.argtypes = [P, i64, P, i32, ctypes.POINTER(SqSpec), ctypes.c_int, ctypes.POINTER(P)]
+        L.sdc_sq_accumulate.argtypes = [P, P, i64, P]
+        L.sdc_sq_finalize.argtypes = [P, P, P, P]
+        L.sdc_sq_timings.argtypes = [P, P]
+        L.sdc_sq_reset.argtypes = [P, P]
+        L.sdc_sq_destroy.argtypes = [P]
         for name in EXPORTS:
             if name not in ("sdc_status_string", "sdc_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -356,3 +368,63 @@ def traj_generate(positions, kind, frames_out, cells=(0, 0, 0), J=1.0, dt=0.01, 
     _check(lib().sdc_traj_generate(_np_ptr(pos), pos.shape[0], ctypes.byref(sp),
                                    _dev_ptr(frames_out, "torch.float32"), frames_out.shape[0],
                                    int(device), _stream_ptr(stream)), "sdc_traj_generate")
+
+
+class StructureFactor:
+    """Eq. (3) at arbitrary wave vectors for any point set, accumulated on the GPU."""
+
+    def __init__(self, positions, q, n_origins, n_lags, origin_stride=1, device=0, timing=False,
+                 connected=False):
+        self._h = None
+        pos = np.ascontiguousarray(positions, dtype=np.float32)
+        qv = np.ascontiguousarray(np.atleast_2d(q), dtype=np.float64)
+        if pos.ndim != 2 or pos.shape[1] != 3 or qv.shape[1] != 3:
+            raise ValueError("positions and q must have shape [n][3]")
+        self.n_sites, self.n_q = pos.shape[0], qv.shape[0]
+        self.n_lags = int(n_lags)
+        self.spec = SqSpec(int(n_origins), int(n_lags), int(origin_stride),
+                           (FLAG_TIMING if timing else 0) | (FLAG_CONNECTED if connected else 0))
+        h = ctypes.c_void_p()
+        _check(lib().sdc_sq_create(_np_ptr(pos), self.n_sites, _np_ptr(qv), self.n_q, ctypes.byref(self.spec),
+                                   int(device), ctypes.byref(h)), "sdc_sq_create")
+        self._h = h
+
+    def accumulate(self, spins, stream=None):
+        """spins: contiguous float32 device tensor [T][N][3]."""
+        if tuple(spins.shape[1:]) != (self.n_sites, 3):
+            raise ValueError("spins must have shape [T][n_sites][3]")
+        _check(lib().sdc_sq_accumulate(self._h, _dev_ptr(spins, "torch.float32"), spins.shape[0],
+                                       _stream_ptr(stream)), "sdc_sq_accumulate")
+
+    def finalize(self, stream=None):
+        """(Sqt [n_q][n_lags], Sqw [n_q][n_lags]) complex128."""
+        sqt = np.zeros((self.n_q, self.n_lags, 2))
+        sqw = np.zeros((self.n_q, self.n_lags, 2))
+        _check(lib().sdc_sq_finalize(self._h, _np_ptr(sqt), _np_ptr(sqw), _stream_ptr(stream)), "sdc_sq_finalize")
+        return sqt[..., 0] + 1j * sqt[..., 1], sqw[..., 0] + 1j * sqw[..., 1]
+
+    def timings(self):
+        """(transform_ms, correlation_ms) of the last accumulate (timing accumulators only)."""
+        ms = np.zeros(2)
+        _check(lib().sdc_sq_timings(self._h, _np_ptr(ms)), "sdc_sq_timings")
+        return float(ms[0]), float(ms[1])
+
+    def reset(self, stream=None):
+        _check(lib().sdc_sq_reset(self._h, _stream_ptr(stream)), "sdc_sq_reset")
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().sdc_sq_destroy(self._h), "sdc_sq_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -138,3 +138,51 @@ def test_no_device_reported_on_host():
                     sdc.corr_spec(8, 16))
     assert st == sdc.ERR_NO_DEVICE
     assert not h.value
+
+
+def _sq_create(pos, q, spec):
+    h = ctypes.c_void_p()
+    p = np.ascontiguousarray(pos, dtype=np.float32)
+    qv = np.ascontiguousarray(q, dtype=np.float64)
+    st = sdc.lib().sdc_sq_create(p.ctypes.data_as(ctypes.c_void_p), p.shape[0], qv.ctypes.data_as(ctypes.c_void_p),
+                                 qv.shape[0], ctypes.byref(spec), 0, ctypes.byref(h))
+    return st, h
+
+
+def test_sq_validation_codes():
+    pos = inputs.ball_positions(50, 2.0, seed=3)
+    q = np.array([[0.1, 0.2, 0.3], [1.0, 0.0, 0.0]])
+    bad_specs = [sdc.SqSpec(0, 8, 1, 0), sdc.SqSpec(4, 0, 1, 0), sdc.SqSpec(4, 2000, 1, 0),
+                 sdc.SqSpec(4, 8, 0, 0), sdc.SqSpec(4, 8, 65, 0), sdc.SqSpec(4, 8, 1, 4),
+                 sdc.SqSpec(4, 8, 1, 8), sdc.SqSpec(5000, 8, 1, 0)]
+    for spec in bad_specs:
+        st, h = _sq_create(pos, q, spec)
+        assert st == sdc.ERR_INVALID_ARG, (spec.n_origins, spec.n_lags, spec.flags, sdc.last_error())
+        assert not h.value
+    good = sdc.SqSpec(4, 8, 1, 0)
+    p_nan = pos.copy()
+    p_nan[7, 1] = np.nan
+    q_inf = q.copy()
+    q_inf[1, 2] = np.inf
+    for pp, qq in [(p_nan, q), (pos, q_inf)]:
+        st, h = _sq_create(pp, qq, good)
+        assert st == sdc.ERR_INVALID_ARG and "non-finite" in sdc.last_error()
+    st, _ = _sq_create(pos, np.zeros((0, 3)), good)
+    assert st == sdc.ERR_INVALID_ARG
+    L = sdc.lib()
+    h = ctypes.c_void_p()
+    assert L.sdc_sq_create(None, 50, None, 1, ctypes.byref(good), 0, ctypes.byref(h)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_sq_accumulate(None, None, 0, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_sq_finalize(None, None, None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_sq_timings(None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_sq_reset(None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_sq_destroy(None) == sdc.OK
+
+
+def test_sq_no_device_reported_on_host():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = _sq_create(inputs.ball_positions(50, 2.0, seed=3), np.zeros((1, 3)), sdc.SqSpec(4, 8, 1, 0))
+    assert st == sdc.ERR_NO_DEVICE
+    assert not h.value

@@ -320,15 +320,18 @@ typedef struct sdc_sq sdc_sq;
  * FP64 after the fp32 inputs (phases q.r and sin/cos in FP64).
  *  positions_host : [n_sites][3] fp32, host, copied; finite.
  *  q_host         : [n_q][3] FP64 wave vectors (radians per unit length),
- *                   host, copied; finite.  1 <= n_q <= 65536.
+ *                   host, copied; finite.  1 <= n_q <= 65536.  The phases
+ *                   must stay below 2^20 rad: max_q |q|_1 times the largest
+ *                   |coordinate| < 2^20 (else UNSUPPORTED).
  *  spec           : origins, lags, stride as in sdc_corr_spec; flags
  *                   SDC_FLAG_CONNECTED subtracts the second term of Eq. (4)
  *                   per pair (the product of the per-site averages over each
  *                   call's origins), SDC_FLAG_TIMING records HIP events.
  *  device         : HIP device ordinal.
- * Allocates all device memory the accumulator needs (the per-site-range
- * partial transforms, at most 1 GiB, and the [n_q][3T] transform).
- * Errors: INVALID_ARG, OOM, NO_DEVICE, HIP.
+ * Allocates all device memory the accumulator needs: the spins packed in
+ * FP64 by chunks of 32 sites (24 bytes per site and frame), the per-site-
+ * range partial transforms (at most 1 GiB) and the [n_q][3T] transform.
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, NO_DEVICE, HIP.
  */
 sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const double* q_host, int32_t n_q,
                          const sdc_sq_spec* spec, int device, sdc_sq** out);
@@ -355,9 +358,10 @@ sdc_status sdc_sq_accumulate(sdc_sq* sq, const float* spins_dev, int64_t n_frame
 sdc_status sdc_sq_finalize(sdc_sq* sq, double* Sqt_host, double* Sqw_host, void* stream);
 
 /* Durations (milliseconds) of the most recent accumulate of an accumulator
- * created with SDC_FLAG_TIMING: ms[0] the phase contraction (with the sum
- * of its site ranges), ms[1] the correlation over origins.  Waits for those
- * events.  Errors: INVALID_ARG, STATE, HIP. */
+ * created with SDC_FLAG_TIMING: ms[0] the FP64 site-chunk packing of the
+ * frames, ms[1] the phase contraction kernel, ms[2] the sum of its site
+ * ranges and the correlation over origins.  Waits for those events.
+ * Errors: INVALID_ARG, STATE, HIP. */
 sdc_status sdc_sq_timings(sdc_sq* sq, double* ms);
 
 /* Zero the accumulated sums and origin total.  Queued on the stream. */

@@ -1010,18 +1010,20 @@ struct sdc_sq {
     int64_t n = 0;
     int n_q = 0;
     int t_used = 0;
+    int t_pad = 0;
     int n_split = 1;
     int64_t sites_per_split = 0;
     std::vector<void*> owned;
     float* d_pos = nullptr;
     double* d_q = nullptr;
+    double* d_pack = nullptr;  // [ceil(n / 32)][t_pad][32][3] packed spins
     double* d_part = nullptr;  // [n_split][n_q][2][3 t_used]
     double* d_F = nullptr;     // [n_q][t_used][3][2]
     double* d_raw = nullptr;   // [n_q][n_lags][2]
     double* d_norg = nullptr;  // [1]
     double* d_out = nullptr;   // [2][n_q][n_lags][2]: S(q, t), S(q, w)
     bool failed = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
 
     ~sdc_sq() {
@@ -1060,8 +1062,19 @@ sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const dou
         if (!std::isfinite(positions_host[x])) return set_err(SDC_ERR_INVALID_ARG, "non-finite position");
     for (int64_t x = 0; x < 3 * (int64_t)n_q; ++x)
         if (!std::isfinite(q_host[x])) return set_err(SDC_ERR_INVALID_ARG, "non-finite wave vector");
+    // the kernels' sine and cosine take |q.r| < 2^20 (a bound through the
+    // largest |q|_1 and the largest coordinate)
+    double q1 = 0.0, rmax = 0.0;
+    for (int32_t k = 0; k < n_q; ++k)
+        q1 = std::max(q1, std::fabs(q_host[3 * k]) + std::fabs(q_host[3 * k + 1]) + std::fabs(q_host[3 * k + 2]));
+    for (int64_t x = 0; x < 3 * n_sites; ++x) rmax = std::max(rmax, (double)std::fabs(positions_host[x]));
+    if (q1 * rmax >= 1048576.0) return set_err(SDC_ERR_UNSUPPORTED, "phases |q.r| may reach 2^20 rad");
     sdc_status s = use_device(device);
     if (s != SDC_OK) return s;
+    {
+        const int e = sdc::prepare_sq_kernels();
+        if (e != 0) return hip_err(e, "kernel attributes");
+    }
     sdc_sq* q = nullptr;
     try {
         q = new sdc_sq();
@@ -1073,6 +1086,8 @@ sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const dou
     q->n = n_sites;
     q->n_q = n_q;
     q->t_used = (spec->n_origins - 1) * spec->origin_stride + spec->n_lags;
+    const int fb = sdc::sq_frames_per_block();
+    q->t_pad = (q->t_used + fb - 1) / fb * fb;
     const int64_t n_cols = 3 * (int64_t)q->t_used;
     // Site ranges: enough workgroups to fill the chip (about 2048), at least
     // four staged chunks per range, partials within kMaxSqPartBytes.
@@ -1098,6 +1113,7 @@ sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const dou
     } while (0)
     SQ_TRY(dalloc(&q->d_pos, (size_t)3 * n_sites, &q->owned));
     SQ_TRY(dalloc(&q->d_q, (size_t)3 * n_q, &q->owned));
+    SQ_TRY(dalloc(&q->d_pack, (size_t)((n_sites + chunk - 1) / chunk) * q->t_pad * 3 * chunk, &q->owned));
     SQ_TRY(dalloc(&q->d_part, (size_t)q->n_split * n_q * 2 * n_cols, &q->owned));
     SQ_TRY(dalloc(&q->d_F, (size_t)n_q * 2 * n_cols, &q->owned));
     SQ_TRY(dalloc(&q->d_raw, out_n, &q->owned));
@@ -1132,6 +1148,8 @@ sdc_status sdc_sq_accumulate(sdc_sq* q, const float* spins_dev, int64_t n_frames
     hipStream_t hs = (hipStream_t)stream;
     sdc::SqTransformArgs ta{};
     ta.frames = spins_dev;
+    ta.packed = q->d_pack;
+    ta.t_pad = q->t_pad;
     ta.pos = q->d_pos;
     ta.q = q->d_q;
     ta.n = q->n;
@@ -1151,10 +1169,12 @@ sdc_status sdc_sq_accumulate(sdc_sq* q, const float* spins_dev, int64_t n_frames
     ca.raw = q->d_raw;
     ca.n_org = q->d_norg;
     if (timing) SDC_HIP(hipEventRecord(q->ev[0], hs), "hipEventRecord");
-    int e = sdc::launch_sq_transform(ta, q->d_F, stream);
+    int e = sdc::launch_sq_pack(ta, stream);
     if (e == 0 && timing) e = (int)hipEventRecord(q->ev[1], hs);
-    if (e == 0) e = sdc::launch_sq_corr(ca, stream);
+    if (e == 0) e = sdc::launch_sq_transform(ta, stream);
     if (e == 0 && timing) e = (int)hipEventRecord(q->ev[2], hs);
+    if (e == 0) e = sdc::launch_sq_corr(ta, ca, stream);
+    if (e == 0 && timing) e = (int)hipEventRecord(q->ev[3], hs);
     if (e != 0) {
         q->failed = true;
         return hip_err(e, "structure factor kernels");
@@ -1192,8 +1212,8 @@ sdc_status sdc_sq_timings(sdc_sq* q, double* ms) {
     if (!ms) return set_err(SDC_ERR_INVALID_ARG, "null output");
     if (!(q->spec.flags & SDC_FLAG_TIMING) || !q->timed)
         return set_err(SDC_ERR_STATE, "no timed accumulate (create with SDC_FLAG_TIMING)");
-    SDC_HIP(hipEventSynchronize(q->ev[2]), "hipEventSynchronize");
-    for (int k = 0; k < 2; ++k) {
+    SDC_HIP(hipEventSynchronize(q->ev[3]), "hipEventSynchronize");
+    for (int k = 0; k < 3; ++k) {
         float t = 0.0f;
         SDC_HIP(hipEventElapsedTime(&t, q->ev[k], q->ev[k + 1]), "hipEventElapsedTime");
         ms[k] = t;

@@ -274,7 +274,9 @@ int launch_sqw(const double* sqt, double* sqw, int n_q, int n_lags, void* stream
 
 // q-resolved S(q, t) of Eq. (3) at arbitrary wave vectors (sdc_sq.hip).
 struct SqTransformArgs {
-    const float* frames;      // [>= n_frames_used][n][3] fp32, caller's site order
+    const float* frames;      // [>= n_frames_used][n][3] fp32, caller's site order (pack input)
+    double* packed;           // [ceil(n / 32)][t_pad][32][3] FP64 (pack output, contraction input)
+    int t_pad;                // n_frames_used rounded up to whole 48-frame column blocks
     const float* pos;         // [n][3] fp32
     const double* q;          // [n_q][3]
     int64_t n;
@@ -285,7 +287,7 @@ struct SqTransformArgs {
     double* part;             // [n_split][n_q][2][3 n_frames_used]
 };
 struct SqCorrArgs {
-    const double* F;          // [n_q][n_frames_used][3][2]
+    double* F;                // [n_q][n_frames_used][3][2], written by the range sum
     int n_q;
     int64_t n_cols;           // 3 n_frames_used
     int n_origins, stride, n_lags;
@@ -296,9 +298,16 @@ struct SqCorrArgs {
 // Workgroups of the transform per site range, and the sites one workgroup
 // stages per step (site ranges are multiples of it).
 int64_t sq_tiles_per_split(int n_q, int n_frames_used);
+// Set the contraction kernel's dynamic-LDS limit on the current device.
+int prepare_sq_kernels();
 int sq_site_chunk();
-int launch_sq_transform(const SqTransformArgs& a, double* F, void* stream);
-int launch_sq_corr(const SqCorrArgs& a, void* stream);
+int sq_frames_per_block();
+// Packs the frames site-chunk-major in FP64 (a.frames -> a.packed).
+int launch_sq_pack(const SqTransformArgs& a, void* stream);
+// The phase contraction alone (partial transforms of the site ranges).
+int launch_sq_transform(const SqTransformArgs& a, void* stream);
+// Sum of the site ranges into a.F, then the origin correlation.
+int launch_sq_corr(const SqTransformArgs& t, const SqCorrArgs& a, void* stream);
 int launch_sq_finalize(const double* raw, const double* n_org, int64_t n_sites, int n_q, int n_lags, double* sqt,
                        double* sqw, void* stream);
 

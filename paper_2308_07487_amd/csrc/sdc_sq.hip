@@ -21,90 +21,215 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kSqQ = 16;                    // wave vectors per workgroup (MFMA rows)
-constexpr int kSqSites = 32;                // sites per LDS chunk (8 MFMA K-steps of 4)
-constexpr int kSqCB = 4;                    // 16-column blocks per wave
-constexpr int kSqCols = 4 * kSqCB * 16;     // spin-matrix columns per workgroup
-constexpr int kSqRow = kSqCols + 16;        // LDS row pitch (floats), staggers the banks
+// sin and cos of x in FP64 for |x| < 2^20, without branches: Cody-Waite
+// reduction x = k pi/2 + r with pi/2 in two parts (FMA), Taylor polynomials
+// of sin r and cos r on |r| <= pi/4 (terms to r^15 and r^16; the first left
+// out is below 1e-16), and the quadrant k mod 4 choosing and signing them.
+// Absolute error a few 1e-16, a quarter of the library routine's work.
+__device__ inline void sincos_small(double x, double* s, double* c) {
+    const double two_over_pi = 0x1.45f306dc9c883p-1;
+    const double pio2_hi = 0x1.921fb54442d18p+0;   // pi/2 rounded to double
+    const double pio2_lo = 0x1.1a62633145c07p-54;  // pi/2 - pio2_hi, rounded
+    const double k = rint(x * two_over_pi);
+    const double r = fma(-k, pio2_lo, fma(-k, pio2_hi, x));
+    const double r2 = r * r;
+    double ps = -1.0 / 1307674368000.0;            // -1/15!
+    ps = fma(ps, r2, 1.0 / 6227020800.0);          //  1/13!
+    ps = fma(ps, r2, -1.0 / 39916800.0);           // -1/11!
+    ps = fma(ps, r2, 1.0 / 362880.0);              //  1/9!
+    ps = fma(ps, r2, -1.0 / 5040.0);               // -1/7!
+    ps = fma(ps, r2, 1.0 / 120.0);                 //  1/5!
+    ps = fma(ps, r2, -1.0 / 6.0);                  // -1/3!
+    const double sn = fma(ps * r2, r, r);
+    double pc = 1.0 / 20922789888000.0;            //  1/16!
+    pc = fma(pc, r2, -1.0 / 87178291200.0);        // -1/14!
+    pc = fma(pc, r2, 1.0 / 479001600.0);           //  1/12!
+    pc = fma(pc, r2, -1.0 / 3628800.0);            // -1/10!
+    pc = fma(pc, r2, 1.0 / 40320.0);               //  1/8!
+    pc = fma(pc, r2, -1.0 / 720.0);                // -1/6!
+    pc = fma(pc, r2, 1.0 / 24.0);                  //  1/4!
+    pc = fma(pc, r2, -0.5);                        // -1/2!
+    const double cs = fma(pc, r2, 1.0);
+    // quadrant: (sin, cos)(k pi/2 + r) = (sn, cs), (cs, -sn), (-sn, -cs), (-cs, sn)
+    const int q = (int)((long long)k & 3);
+    const double s0 = (q & 1) ? cs : sn;
+    const double c0 = (q & 1) ? sn : cs;
+    *s = (q & 2) ? -s0 : s0;
+    *c = ((q + 1) & 2) ? -c0 : c0;
+}
 
-// One workgroup: 16 wave vectors x 256 columns (f, a) x one range of sites.
-// Per chunk of 32 sites the workgroup computes the 512 phases (cos, -sin of
-// q.r in FP64) and stages the spins of its columns in LDS; each wave then runs
-// 8 K-steps of 4 sites, two FP64 MFMAs (real and imaginary phase rows) per
-// 16-column block.  The partial transform of the site range goes to its own
-// slice of `part` (no atomics; the slices are summed in a fixed order).
-__global__ __launch_bounds__(256) void sq_transform_kernel(SqTransformArgs a) {
-    __shared__ double ph[2][kSqSites][kSqQ];
-    __shared__ float sb[kSqSites][kSqRow];
+constexpr int kSqWaves = 4;                 // consumer waves (MFMA); as many producer waves
+constexpr int kSqThreads = 2 * 64 * kSqWaves;
+constexpr int kSqQ = 16 * kSqWaves;         // wave vectors per workgroup: one 16-row block per consumer
+constexpr int kSqSites = 32;                // sites per chunk (8 MFMA K-steps of 4)
+constexpr int kSqCB = 9;                    // 16-column blocks, shared by the consumers
+constexpr int kSqCols = kSqCB * 16;         // 144 spin-matrix columns = 48 whole frames
+constexpr int kSqFrames = kSqCols / 3;
+constexpr int kSqPitch = 3 * kSqSites + 4;  // LDS doubles per staged frame (padded against bank conflicts)
+constexpr int kSqPhBuf = 2 * kSqSites * kSqQ;    // doubles of one phase buffer (cos, -sin)
+constexpr int kSqSbBuf = kSqFrames * kSqPitch;   // doubles of one spin buffer
+constexpr int kSqLdsBytes = 2 * (kSqPhBuf + kSqSbBuf) * (int)sizeof(double);
+static_assert(kSqCols % 3 == 0, "a column range must cover whole frames");
+static_assert(kSqLdsBytes <= 160 * 1024, "two chunk buffers must fit in LDS");
+
+constexpr int kSqProducers = 64 * kSqWaves;
+constexpr int kSqPhPer = kSqSites * kSqQ / kSqProducers;         // phases per producer thread
+constexpr int kSqSbPer = kSqFrames * 3 * kSqSites / kSqProducers;  // spin values per producer thread
+static_assert(kSqPhPer * kSqProducers == kSqSites * kSqQ && kSqProducers % kSqQ == 0, "phase split");
+static_assert(kSqSbPer * kSqProducers == kSqFrames * 3 * kSqSites && kSqSbPer % 2 == 0, "spin split");
+static_assert(kSqPitch % 2 == 0, "16-byte LDS rows");
+
+// Producer side: the phases of the 64 wave vectors at the 32 sites of chunk
+// j0 and the chunk's spins of 48 frames (one contiguous FP64 block of the
+// packed spins) into one buffer.  Producer thread p keeps wave vector p % 64
+// (qv, zero past n_q) and takes sites p / 64 + 4 i; every global load of the
+// chunk is issued before the first is used.
+__device__ __forceinline__ void sq_produce(const SqTransformArgs& a, int ptid, const double (&qv)[3], int64_t f_first,
+                                           int64_t j0, int64_t je, double* __restrict__ ph,
+                                           double* __restrict__ sb) {
+    float px[kSqPhPer], py[kSqPhPer], pz[kSqPhPer];
+#pragma unroll
+    for (int i = 0; i < kSqPhPer; ++i) {
+        const int64_t j = j0 + ptid / kSqQ + (kSqProducers / kSqQ) * i;
+        const bool in = j < je;
+        px[i] = in ? a.pos[3 * j] : 0.0f;
+        py[i] = in ? a.pos[3 * j + 1] : 0.0f;
+        pz[i] = in ? a.pos[3 * j + 2] : 0.0f;
+    }
+    // the chunk's 48 frames x 32 sites x 3 components, as pairs of doubles
+    const double2* src =
+        (const double2*)(a.packed + ((j0 / kSqSites) * a.t_pad + f_first) * (3 * kSqSites));
+    double2 v[kSqSbPer / 2];
+#pragma unroll
+    for (int i = 0; i < kSqSbPer / 2; ++i) v[i] = src[ptid + kSqProducers * i];
+#pragma unroll
+    for (int i = 0; i < kSqPhPer; ++i) {
+        const int64_t j = j0 + ptid / kSqQ + (kSqProducers / kSqQ) * i;
+        double cs = 0.0, sn = 0.0;
+        if (j < je) {
+            const double th = qv[0] * (double)px[i] + qv[1] * (double)py[i] + qv[2] * (double)pz[i];
+            sincos_small(th, &sn, &cs);
+        }
+        const int e = ptid + kSqProducers * i;  // = site * 64 + wave vector
+        ph[e] = cs;                             // Re exp(-i q.r), [site][q]
+        ph[kSqSites * kSqQ + e] = -sn;          // Im exp(-i q.r)
+    }
+#pragma unroll
+    for (int i = 0; i < kSqSbPer / 2; ++i) {
+        const int e = ptid + kSqProducers * i;  // pair index: frame e / 48, values 2 (e % 48), +1
+        const int fl = e / (3 * kSqSites / 2), r = 2 * (e - fl * (3 * kSqSites / 2));
+        *(double2*)(sb + fl * kSqPitch + r) = v[i];
+    }
+}
+
+// Packed spins for the contraction: P[c][f][s][a] = S_j^a(f), j = 32 c + s,
+// FP64, zero for sites past N and frames past n_frames_used (t_pad frames
+// per chunk, a multiple of 48), so that a chunk's 48 frames are one
+// contiguous block.
+__global__ __launch_bounds__(256) void sq_pack_kernel(SqTransformArgs a) {
+    const int64_t per_chunk = (int64_t)a.t_pad * 3 * kSqSites;
+    const int64_t total = (a.n + kSqSites - 1) / kSqSites * per_chunk;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ch = x / per_chunk, rem = x - ch * per_chunk;
+        const int64_t f = rem / (3 * kSqSites);
+        const int r = (int)(rem - f * 3 * kSqSites);
+        const int64_t j = ch * kSqSites + r / 3;
+        a.packed[x] = (f < a.n_frames_used && j < a.n) ? (double)a.frames[(f * a.n + j) * 3 + r % 3] : 0.0;
+    }
+}
+
+// One workgroup: 64 wave vectors x 144 columns (48 frames x 3 components) x
+// one range of sites, in chunks of 32 sites with two LDS buffers.  Four
+// producer waves fill the next chunk's buffer (64 x 32 phases, cos and -sin
+// of q.r in FP64, and the spins) while four consumer waves run the current
+// chunk: consumer w takes its 16 wave vectors through 8 K-steps of 4 sites,
+// two FP64 MFMAs (real and imaginary phase rows) per 16-column block sharing
+// the spin operand.  One barrier per chunk.  Spins are read from memory once
+// per 64 wave vectors and each phase is computed once per 144 columns.  The
+// partial transform of the site range goes to its own slice of `part` (no
+// atomics; the slices are summed in a fixed order).
+__global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransformArgs a) {
+    extern __shared__ double lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool producer = wave >= kSqWaves;
     const int q0 = blockIdx.x * kSqQ;
-    const int64_t c0 = (int64_t)blockIdx.y * kSqCols;
+    const int64_t f_first = (int64_t)blockIdx.y * kSqFrames;
+    const int64_t c0 = 3 * f_first;
     const int64_t n_cols = 3 * (int64_t)a.n_frames_used;
     const int64_t jb = (int64_t)blockIdx.z * a.sites_per_split;
     const int64_t je = jb + a.sites_per_split < a.n ? jb + a.sites_per_split : a.n;
-    // frames whose three columns meet [c0, c0 + kSqCols)
-    const int64_t f_first = c0 / 3;
-    const int n_f = (int)((c0 + kSqCols - 1) / 3 - f_first + 1);
+    // Producer and consumer waves run separate loops with the same barrier
+    // count (one before the first chunk, one per chunk), so the consumers'
+    // accumulators are not live in the producers' code.
+    if (producer) {
+        const int ptid = tid - 64 * kSqWaves;
+        double qv[3] = {0.0, 0.0, 0.0};  // zero past n_q: rows nobody stores
+        if (q0 + ptid % kSqQ < a.n_q) {
+            qv[0] = a.q[3 * (q0 + ptid % kSqQ)];
+            qv[1] = a.q[3 * (q0 + ptid % kSqQ) + 1];
+            qv[2] = a.q[3 * (q0 + ptid % kSqQ) + 2];
+        }
+        sq_produce(a, ptid, qv, f_first, jb, je, lds, lds + 2 * kSqPhBuf);
+        __syncthreads();
+        int nxt = 1;
+        for (int64_t j0 = jb; j0 < je; j0 += kSqSites) {
+            if (j0 + kSqSites < je)
+                sq_produce(a, ptid, qv, f_first, j0 + kSqSites, je, lds + nxt * kSqPhBuf,
+                           lds + 2 * kSqPhBuf + nxt * kSqSbBuf);
+            __syncthreads();  // the consumers are done with the other buffer
+            nxt ^= 1;
+        }
+        return;
+    }
+    const bool active = q0 + 16 * wave < a.n_q;  // wave-uniform
+    // LDS offset of this lane's column in each block (frame row, component)
+    int boff[kSqCB];
+#pragma unroll
+    for (int b = 0; b < kSqCB; ++b) {
+        const int c = b * 16 + (lane & 15);
+        boff[b] = (c / 3) * kSqPitch + c % 3;
+    }
     f64x4 acc_re[kSqCB], acc_im[kSqCB];
 #pragma unroll
     for (int b = 0; b < kSqCB; ++b) {
         acc_re[b] = f64x4{0.0, 0.0, 0.0, 0.0};
         acc_im[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
+    __syncthreads();  // the first chunk is staged
+    int cur = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kSqSites) {
-        __syncthreads();  // the previous chunk has been consumed
-        for (int e = tid; e < kSqSites * kSqQ; e += 256) {
-            const int s = e / kSqQ, qi = e % kSqQ;
-            const int64_t j = j0 + s;
-            const int qq = q0 + qi;
-            double cs = 0.0, sn = 0.0;
-            if (j < je && qq < a.n_q) {
-                const double th = a.q[3 * qq] * (double)a.pos[3 * j] + a.q[3 * qq + 1] * (double)a.pos[3 * j + 1] +
-                                  a.q[3 * qq + 2] * (double)a.pos[3 * j + 2];
-                sincos(th, &sn, &cs);
-            }
-            ph[0][s][qi] = cs;   // Re exp(-i q.r)
-            ph[1][s][qi] = -sn;  // Im exp(-i q.r)
-        }
-        // spins of the chunk: frame-major so that each frame's sites x 3
-        // components are one contiguous run of the [T][N][3] array
-        for (int e = tid; e < n_f * 3 * kSqSites; e += 256) {
-            const int fl = e / (3 * kSqSites);
-            const int r = e - fl * 3 * kSqSites;
-            const int s = r / 3, al = r - 3 * s;
-            const int64_t f = f_first + fl;
-            const int64_t c = 3 * f + al - c0;
-            if (c < 0 || c >= kSqCols) continue;
-            const int64_t j = j0 + s;
-            float v = 0.0f;
-            if (f < a.n_frames_used && j < je) v = a.frames[(f * a.n + j) * 3 + al];
-            sb[s][c] = v;
-        }
-        __syncthreads();
+        if (active) {
+            const double* ph = lds + cur * kSqPhBuf;
+            const double* sb = lds + 2 * kSqPhBuf + cur * kSqSbBuf;
+#pragma unroll 2
+            for (int k4 = 0; k4 < kSqSites; k4 += 4) {
+                // A[i][k] = phase of wave vector i at site k: lane i + 16 k;
+                // B[k][c] = spin column c at site k: lane c + 16 k
+                const int s = k4 + (lane >> 4);
+                const double are = ph[s * kSqQ + 16 * wave + (lane & 15)];
+                const double aim = ph[kSqSites * kSqQ + s * kSqQ + 16 * wave + (lane & 15)];
 #pragma unroll
-        for (int k4 = 0; k4 < kSqSites; k4 += 4) {
-            // A[i][k] = phase of wave vector i at site k: lane i + 16 k;
-            // B[k][c] = spin column c at site k: lane c + 16 k
-            const int s = k4 + (lane >> 4);
-            const double are = ph[0][s][lane & 15], aim = ph[1][s][lane & 15];
-#pragma unroll
-            for (int b = 0; b < kSqCB; ++b) {
-                const double bv = (double)sb[s][(wave * kSqCB + b) * 16 + (lane & 15)];
-                acc_re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv, acc_re[b], 0, 0, 0);
-                acc_im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bv, acc_im[b], 0, 0, 0);
+                for (int b = 0; b < kSqCB; ++b) {
+                    const double bv = sb[boff[b] + 3 * s];
+                    acc_re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv, acc_re[b], 0, 0, 0);
+                    acc_im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bv, acc_im[b], 0, 0, 0);
+                }
             }
         }
+        __syncthreads();  // done with `cur`; the producers have filled the other buffer
+        cur ^= 1;
     }
+    if (!active) return;
     // D[i][c] of the FP64 16x16x4 form: lane l, item v holds row 4 v + l / 16
     // of column l % 16 (rows interleave across the lane groups, unlike the
     // FP32 forms)
     double* out = a.part + (int64_t)blockIdx.z * a.n_q * 2 * n_cols;
 #pragma unroll
     for (int b = 0; b < kSqCB; ++b) {
-        const int64_t c = c0 + (wave * kSqCB + b) * 16 + (lane & 15);
+        const int64_t c = c0 + b * 16 + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int qq = q0 + 4 * v + (lane >> 4);
+            const int qq = q0 + 16 * wave + 4 * v + (lane >> 4);
             if (qq < a.n_q && c < n_cols) {
                 out[(int64_t)qq * 2 * n_cols + c] = acc_re[b][v];
                 out[((int64_t)qq * 2 + 1) * n_cols + c] = acc_im[b][v];
@@ -171,8 +296,7 @@ __global__ __launch_bounds__(256) void sq_norm_kernel(const double* __restrict__
 }
 
 dim3 sq_transform_grid(int n_q, int n_frames_used, int n_split) {
-    const int64_t n_cols = 3 * (int64_t)n_frames_used;
-    return dim3((unsigned)((n_q + kSqQ - 1) / kSqQ), (unsigned)((n_cols + kSqCols - 1) / kSqCols),
+    return dim3((unsigned)((n_q + kSqQ - 1) / kSqQ), (unsigned)((n_frames_used + kSqFrames - 1) / kSqFrames),
                 (unsigned)n_split);
 }
 
@@ -190,17 +314,30 @@ int64_t sq_tiles_per_split(int n_q, int n_frames_used) {
 
 int sq_site_chunk() { return kSqSites; }
 
-int launch_sq_transform(const SqTransformArgs& a, double* F, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(sq_transform_kernel, sq_transform_grid(a.n_q, a.n_frames_used, a.n_split), dim3(256), 0, s,
-                       a);
-    const int64_t per = (int64_t)a.n_q * 2 * 3 * (int64_t)a.n_frames_used;
-    hipLaunchKernelGGL(sq_reduce_kernel, dim3((unsigned)blocks_for(per)), dim3(256), 0, s, a, F);
+int prepare_sq_kernels() {
+    return (int)hipFuncSetAttribute((const void*)sq_transform_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kSqLdsBytes);
+}
+
+int sq_frames_per_block() { return kSqFrames; }
+
+int launch_sq_pack(const SqTransformArgs& a, void* stream) {
+    const int64_t total = (a.n + kSqSites - 1) / kSqSites * (int64_t)a.t_pad * 3 * kSqSites;
+    hipLaunchKernelGGL(sq_pack_kernel, dim3((unsigned)blocks_for(total)), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
-int launch_sq_corr(const SqCorrArgs& a, void* stream) {
-    hipLaunchKernelGGL(sq_corr_kernel, dim3((unsigned)a.n_q), dim3(256), 0, (hipStream_t)stream, a);
+int launch_sq_transform(const SqTransformArgs& a, void* stream) {
+    hipLaunchKernelGGL(sq_transform_kernel, sq_transform_grid(a.n_q, a.n_frames_used, a.n_split), dim3(kSqThreads),
+                       kSqLdsBytes, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+int launch_sq_corr(const SqTransformArgs& t, const SqCorrArgs& a, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t per = (int64_t)t.n_q * 2 * 3 * (int64_t)t.n_frames_used;
+    hipLaunchKernelGGL(sq_reduce_kernel, dim3((unsigned)blocks_for(per)), dim3(256), 0, s, t, a.F);
+    hipLaunchKernelGGL(sq_corr_kernel, dim3((unsigned)a.n_q), dim3(256), 0, s, a);
     return (int)hipGetLastError();
 }
 

@@ -404,10 +404,11 @@ class StructureFactor:
         return sqt[..., 0] + 1j * sqt[..., 1], sqw[..., 0] + 1j * sqw[..., 1]
 
     def timings(self):
-        """(transform_ms, correlation_ms) of the last accumulate (timing accumulators only)."""
-        ms = np.zeros(2)
+        """(pack_ms, contraction_ms, reduce_and_correlation_ms) of the last accumulate
+        (timing accumulators only)."""
+        ms = np.zeros(3)
         _check(lib().sdc_sq_timings(self._h, _np_ptr(ms)), "sdc_sq_timings")
-        return float(ms[0]), float(ms[1])
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def reset(self, stream=None):
         _check(lib().sdc_sq_reset(self._h, _stream_ptr(stream)), "sdc_sq_reset")

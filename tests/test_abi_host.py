@@ -169,6 +169,8 @@ def test_sq_validation_codes():
         assert st == sdc.ERR_INVALID_ARG and "non-finite" in sdc.last_error()
     st, _ = _sq_create(pos, np.zeros((0, 3)), good)
     assert st == sdc.ERR_INVALID_ARG
+    st, _ = _sq_create(pos * np.float32(1e5), np.array([[3.0, 2.0, 1.0]]), good)  # |q.r| up to ~1e6 rad
+    assert st == sdc.ERR_UNSUPPORTED and "2^20" in sdc.last_error()
     L = sdc.lib()
     h = ctypes.c_void_p()
     assert L.sdc_sq_create(None, 50, None, 1, ctypes.byref(good), 0, ctypes.byref(h)) == sdc.ERR_INVALID_ARG

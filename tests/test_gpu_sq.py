@@ -77,6 +77,24 @@ def test_sq_matches_oracle_ball(torch_dev, S, orc, n, n_q, n_o, n_L, stride):
         np.testing.assert_allclose(sqt, np.broadcast_to(direct, sqt.shape), rtol=0, atol=1e-14)
 
 
+def test_sq_large_phases(torch_dev, S, orc):
+    """Phases q.r up to about 5e5 rad (points in a ball of radius 2000, |q|
+    up to 170): the kernels' sine and cosine reduce the argument by pi/2 in
+    two parts.  The FP64 rounding of q.r itself, about 1e-16 |q.r|, is the
+    same on both sides only up to the order of the three products, so the
+    bar is 1e-16 |q.r|_max relative."""
+    _say("sq large phases")
+    pos = inputs.ball_positions(500, 2000.0, seed=61)
+    fr = inputs.random_unit_frames(10, 500, seed=62)
+    q = _random_q(24, 100.0, seed=63)
+    sqt, _ = _run(torch_dev, S, pos, q, [fr], 4, 6)
+    ref = orc.structure_factor_q(pos, fr, 4, list(range(6)), q)
+    ph = float(np.max(np.abs(pos.astype(np.float64) @ q.T)))
+    e = _err(sqt, ref)
+    print(f"  max |q.r| {ph:.3g} rad, normwise error {e:.2e}", flush=True)
+    assert ph > 1e5 and e <= max(BAR, 20 * 2.0 ** -52 * ph)
+
+
 def test_sq_connected_bcc_incommensurate(torch_dev, S, orc):
     _say("sq connected, bcc 4x3x5 positions, incommensurate q, stride 3")
     L = (4, 3, 5)

@@ -21,7 +21,8 @@ Each function states the paper passage it follows (arXiv 2308.07487):
 - ``finalize``         per-bin normalisation, site sum (Sec. 1: summing the
                        correlation over all sites) and the windowed time
                        transform of Sec. 2.2.
-- ``ll_rk4``           Eq. (2) with the exchange term of Eq. (1), RK4 without
+- ``ll_rk4``           Eq. (2) with the Hamiltonian of Eq. (1) (exchange, DMI,
+                       single-ion anisotropy, field), RK4 without
                        renormalisation (Sec. 3.1).
 - ``philox`` / ``init_state``  Philox4x32-10 (Salmon et al., SC'11) seeded
                        initial states.
@@ -79,12 +80,14 @@ def lib():
         L.oracle_dft.argtypes = [P, i32, P]
         L.oracle_finalize.argtypes = [P, P, i64, i32, i64, P, P, P, P, P, P, P]
         L.oracle_ll_rk4.argtypes = [i64, P, P, P, P, f64, i64, P]
+        L.oracle_ll_rk4_full.argtypes = [i64, P, P, P, P, f64, f64, P, f64, i64, P]
         L.oracle_philox.argtypes = [u64, u32, i64, i64, P]
         L.oracle_init_state.argtypes = [u64, i64, ctypes.c_int, f64, P]
         L.oracle_philox_block.argtypes = [P, P, P]
         for name in ("oracle_n_bins", "oracle_pair_keys", "oracle_binned_corr",
                      "oracle_binned_corr_select", "oracle_self_corr", "oracle_dft",
-                     "oracle_finalize", "oracle_ll_rk4", "oracle_philox", "oracle_init_state",
+                     "oracle_finalize", "oracle_ll_rk4", "oracle_ll_rk4_full", "oracle_philox",
+                     "oracle_init_state",
                      "oracle_philox_block", "oracle_mean_product", "oracle_self_mean_product"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -280,16 +283,24 @@ def finalize(H, counts, n_sites, n_org, self_raw):
     return C, Cs, Cf, Ss[:, 0] + 1j * Ss[:, 1], Sf[:, 0] + 1j * Sf[:, 1]
 
 
-def ll_rk4(row, col, J, init, dt, n_frames):
-    """RK4 frames [n_frames][n][3] (FP64) for dS_i/dt = (sum_j J_ij S_j) x S_i."""
+def ll_rk4(row, col, J, init, dt, n_frames, D=None, A=0.0, Hz=0.0):
+    """RK4 frames [n_frames][n][3] (FP64) for Eq. (2) with the Hamiltonian of
+    Eq. (1): dS_i/dt = h_i x S_i, h_i = sum_j (J_ij S_j + D_ij x S_j)
+    - 2 A S_i^z z - H_z z.  CSR bonds (row, col, J); D: [nnz][3] DMI vectors of
+    the ordered pairs (D_ji = -D_ij) or None."""
     row = np.ascontiguousarray(row, dtype=np.int64)
     col = np.ascontiguousarray(col, dtype=np.int32)
     J = np.ascontiguousarray(J, dtype=np.float64)
     init = np.ascontiguousarray(init, dtype=np.float32)
     n = init.shape[0]
     out = np.zeros((int(n_frames), n, 3), dtype=np.float64)
-    _check(lib().oracle_ll_rk4(n, _ptr(row), _ptr(col), _ptr(J), _ptr(init), float(dt),
-                               int(n_frames), _ptr(out)), "ll_rk4")
+    Dp = None
+    if D is not None:
+        D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1, 3)
+        assert D.shape[0] == col.shape[0]
+        Dp = _ptr(D)
+    _check(lib().oracle_ll_rk4_full(n, _ptr(row), _ptr(col), _ptr(J), Dp, float(A), float(Hz), _ptr(init),
+                                    float(dt), int(n_frames), _ptr(out)), "ll_rk4")
     return out
 
 

@@ -552,25 +552,38 @@ int oracle_finalize(const double *H, const uint64_t *counts, int64_t n_bins,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Landau-Lifshitz RK4 (Eq. 2, exchange part of Eq. 1)                       */
+/* Landau-Lifshitz RK4 (Eq. 2 with the Hamiltonian of Eq. 1)                 */
 /* ------------------------------------------------------------------------ */
 
 /*
- * Exchange couplings as a CSR list: for site i, neighbours col[row[i]..row[i+1])
- * with couplings J[...].  H = sum over bonds J_ij S_i . S_j (each bond once),
- * so dH/dS_i = sum_j J_ij S_j, and Eq. (2) gives dS_i/dt = (sum_j J_ij S_j) x S_i.
+ * Couplings as a CSR list: for site i, neighbours col[row[i]..row[i+1]) with
+ * exchange J[...] and DMI vectors Dv[3 (...)] of the ordered pair (i, j),
+ * D_ji = -D_ij.  H = sum over bonds (each once) of J_ij S_i.S_j
+ * - D_ij.(S_i x S_j), minus A sum_i (S_i^z)^2 and H_z sum_i S_i^z (Eq. (1)),
+ * so dH/dS_i = sum_j (J_ij S_j + D_ij x S_j) - 2 A S_i^z z - H_z z, and
+ * Eq. (2) gives dS_i/dt = (dH/dS_i) x S_i.
  */
 static void oderiv(int64_t n, const int64_t *row, const int32_t *col,
-                   const double *J, const double *S, double *D) {
+                   const double *J, const double *Dv, double A, double Hz,
+                   const double *S, double *D) {
     for (int64_t i = 0; i < n; ++i) {
+        const double *si = S + 3 * i;
+        /* h = dH/dS_i of Eq. (1): exchange, DMI, anisotropy, field */
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
         for (int64_t e = row[i]; e < row[i + 1]; ++e) {
             const double *sj = S + 3 * (int64_t)col[e];
             h0 += J[e] * sj[0];
             h1 += J[e] * sj[1];
             h2 += J[e] * sj[2];
+            if (Dv) {
+                /* -D_ij.(S_i x S_j) = S_i.(D_ij x S_j): gradient D_ij x S_j */
+                const double *d = Dv + 3 * e;
+                h0 += d[1] * sj[2] - d[2] * sj[1];
+                h1 += d[2] * sj[0] - d[0] * sj[2];
+                h2 += d[0] * sj[1] - d[1] * sj[0];
+            }
         }
-        const double *si = S + 3 * i;
+        h2 += -2.0 * A * si[2] - Hz;
         D[3 * i + 0] = h1 * si[2] - h2 * si[1];
         D[3 * i + 1] = h2 * si[0] - h0 * si[2];
         D[3 * i + 2] = h0 * si[1] - h1 * si[0];
@@ -578,13 +591,18 @@ static void oderiv(int64_t n, const int64_t *row, const int32_t *col,
 }
 
 /*
- * Classical RK4 with step dt, no renormalisation.  init: [n][3] (fp32 input
- * state, promoted).  frames_out: [n_frames][n][3] fp64; frame 0 is the
- * initial state and frame f the state after f steps.
+ * Classical RK4 with step dt, no renormalisation, for Eq. (2) with the
+ * Hamiltonian of Eq. (1): dS_i/dt = h_i x S_i,
+ *   h_i = sum_j J_ij S_j + sum_j D_ij x S_j - 2 A S_i^z z - H_z z,
+ * CSR bonds (row, col, J; Dv: [nnz][3] DMI vectors of the ordered pairs, or
+ * NULL for none).  init: [n][3] (fp32 input state, promoted).  frames_out:
+ * [n_frames][n][3] fp64; frame 0 is the initial state and frame f the state
+ * after f steps.
  */
-int oracle_ll_rk4(int64_t n, const int64_t *row, const int32_t *col,
-                  const double *J, const float *init, double dt,
-                  int64_t n_frames, double *frames_out) {
+int oracle_ll_rk4_full(int64_t n, const int64_t *row, const int32_t *col,
+                       const double *J, const double *Dv, double A, double Hz,
+                       const float *init, double dt, int64_t n_frames,
+                       double *frames_out) {
     if (n <= 0 || n_frames <= 0) return OR_EINVAL;
     size_t m = 3 * (size_t)n;
     double *S = (double *)malloc(sizeof(double) * m);
@@ -600,19 +618,26 @@ int oracle_ll_rk4(int64_t n, const int64_t *row, const int32_t *col,
     for (size_t x = 0; x < m; ++x) S[x] = (double)init[x];
     memcpy(frames_out, S, sizeof(double) * m);
     for (int64_t f = 1; f < n_frames; ++f) {
-        oderiv(n, row, col, J, S, k1);
+        oderiv(n, row, col, J, Dv, A, Hz, S, k1);
         for (size_t x = 0; x < m; ++x) T[x] = S[x] + 0.5 * dt * k1[x];
-        oderiv(n, row, col, J, T, k2);
+        oderiv(n, row, col, J, Dv, A, Hz, T, k2);
         for (size_t x = 0; x < m; ++x) T[x] = S[x] + 0.5 * dt * k2[x];
-        oderiv(n, row, col, J, T, k3);
+        oderiv(n, row, col, J, Dv, A, Hz, T, k3);
         for (size_t x = 0; x < m; ++x) T[x] = S[x] + dt * k3[x];
-        oderiv(n, row, col, J, T, k4);
+        oderiv(n, row, col, J, Dv, A, Hz, T, k4);
         for (size_t x = 0; x < m; ++x)
             S[x] += dt / 6.0 * (k1[x] + 2.0 * k2[x] + 2.0 * k3[x] + k4[x]);
         memcpy(frames_out + (size_t)f * m, S, sizeof(double) * m);
     }
     free(S); free(T); free(k1); free(k2); free(k3); free(k4);
     return OR_OK;
+}
+
+/* The exchange-only form (no DMI, anisotropy or field). */
+int oracle_ll_rk4(int64_t n, const int64_t *row, const int32_t *col,
+                  const double *J, const float *init, double dt,
+                  int64_t n_frames, double *frames_out) {
+    return oracle_ll_rk4_full(n, row, col, J, NULL, 0.0, 0.0, init, dt, n_frames, frames_out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -680,3 +680,75 @@ def test_structure_factor_q_connected(orc):
     for qi, mq in enumerate(ms):
         ph = np.exp(-1j * (d @ (2 * np.pi * mq / np.array(L))))
         np.testing.assert_allclose((H @ ph) / (n * n_o), S[qi], rtol=0, atol=1e-12)
+
+
+def _sc_bonds_dmi(L, J, D):
+    """sc nearest-neighbour CSR with bulk DMI vectors D_ij = D (r_j - r_i)/|r_j - r_i|
+    (minimal image), built from coordinates."""
+    pos = inputs.sc_positions(L)
+    row, col, Jv, z = _nn_csr(pos, L, "sc", J)
+    deltas = np.array([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)], dtype=np.float64)
+    Dv = np.tile(D * deltas, (pos.shape[0], 1))
+    return pos, row, col, Jv, Dv, z
+
+
+def test_rk4_cone_wave_full_model_closed_form(orc):
+    """Eq. (2) with every term of Eq. (1) on an sc lattice: a cone spin wave
+    S = (sin th cos phi, sin th sin phi, cos th), phi = q z - w t, q along z,
+    is an exact solution with
+        w = cos th [J (gamma_q - 6) - 2 D sin q + 2 A] + H_z,  gamma_q = 4 + 2 cos q,
+    for bulk DMI (D along the bond), anisotropy A and field H_z along z.  A
+    flipped sign of any one term moves w by O(0.1)."""
+    L = (3, 3, 8)
+    J, D, A, Hz, theta, dt, nf = -1.0, 0.35, 0.25, 0.5, 0.6, 0.01, 301
+    pos, row, col, Jv, Dv, z = _sc_bonds_dmi(L, J, D)
+    for m in (0, 1, 3):
+        q = 2 * np.pi * m / L[2]
+        w = np.cos(theta) * (J * (4 + 2 * np.cos(q) - z) - 2 * D * np.sin(q) + 2 * A) + Hz
+        qv = np.array([0.0, 0.0, q])
+        init = inputs.spiral_frames(pos, qv, theta, w, 1, dt)[0]
+        out = orc.ll_rk4(row, col, Jv, init, dt, nf, D=Dv, A=A, Hz=Hz)
+        exact = inputs.spiral_frames(pos, qv, theta, w, nf, dt).astype(np.float64)
+        assert np.abs(out - exact).max() < 3e-7, m
+        for dw in (4 * D * np.sin(q) * np.cos(theta), 4 * A * np.cos(theta), 2 * Hz):
+            if dw > 1e-6:
+                wrong = inputs.spiral_frames(pos, qv, theta, w + dw, nf, dt).astype(np.float64)
+                assert np.abs(out - wrong).max() > 1e-2
+
+
+def _energy(S, row, col, Jv, Dv, A, Hz):
+    """Eq. (1) written out: each bond once (i < j), DMI vector of (i, j)."""
+    E = 0.0
+    for i in range(S.shape[0]):
+        for e in range(row[i], row[i + 1]):
+            j = col[e]
+            if j > i:
+                E += Jv[e] * (S[i] @ S[j]) - Dv[e] @ np.cross(S[i], S[j])
+    return E - A * np.sum(S[:, 2] ** 2) - Hz * np.sum(S[:, 2])
+
+
+def test_rk4_full_model_conserves_energy(orc):
+    """The Landau-Lifshitz flow conserves the Hamiltonian it is derived from
+    and every |S_i|; a wrong sign of the DMI gradient, of the anisotropy or of
+    the field breaks the energy balance."""
+    L = (3, 3, 3)
+    J, D, A, Hz, dt, nf = 1.0, 0.4, 0.3, 0.7, 0.005, 401
+    pos, row, col, Jv, Dv, _ = _sc_bonds_dmi(L, J, D)
+    rng = np.random.default_rng(5)
+    Jv = Jv * rng.choice([-1.0, 1.0], size=Jv.shape)
+    # symmetric random signs: J_ij = J_ji
+    key = {}
+    for i in range(pos.shape[0]):
+        for e in range(row[i], row[i + 1]):
+            key.setdefault((min(i, col[e]), max(i, col[e])), Jv[e])
+            Jv[e] = key[(min(i, col[e]), max(i, col[e]))]
+    init = inputs.random_unit_frames(1, pos.shape[0], seed=6)[0]
+    out = orc.ll_rk4(row, col, Jv, init, dt, nf, D=Dv, A=A, Hz=Hz)
+    E0 = _energy(out[0], row, col, Jv, Dv, A, Hz)
+    E1 = _energy(out[-1], row, col, Jv, Dv, A, Hz)
+    assert abs(E1 - E0) < 1e-8 * pos.shape[0]
+    assert np.abs(np.linalg.norm(out[-1], axis=1) - np.linalg.norm(out[0], axis=1)).max() < 1e-8
+    assert np.abs(out[-1] - out[0]).max() > 0.1
+    for wrong in (dict(D=-Dv, A=A, Hz=Hz), dict(D=Dv, A=-A, Hz=Hz)):
+        o2 = orc.ll_rk4(row, col, Jv, init, dt, nf, **wrong)
+        assert abs(_energy(o2[-1], row, col, Jv, Dv, A, Hz) - E0) > 1e-4

@@ -414,12 +414,21 @@ typedef struct {
     double sigma;       /* PERTURBED_Z tangent width (radians)                */
     uint64_t seed;      /* Philox4x32-10 key                                  */
     const float* init_dev; /* GIVEN: [n_sites][3] fp32 device memory          */
+    double D;           /* DMI strength: D_ij = D (r_j - r_i)/|r_j - r_i|     */
+                        /* (bulk form, minimal image on lattices), Eq. (1)    */
+    double A;           /* single-ion anisotropy, -A sum_i (S_i^z)^2          */
+    double Hz;          /* field along z, -H_z sum_i S_i^z                    */
 } sdc_traj_spec;
 
 /*
- * Integrate dS_i/dt = (sum_j J_ij S_j) x S_i with classical RK4 (no
- * renormalisation) in FP32 and write frames [n_frames][n_sites][3] fp32 into
- * frames_dev (frame 0 = initial state, frame f = after f steps).
+ * Integrate Eq. (2) with the Hamiltonian of Eq. (1),
+ *     H = sum_<ij> [J_ij S_i.S_j - D_ij.(S_i x S_j)] - A sum_i (S_i^z)^2
+ *         - H_z sum_i S_i^z,
+ *     dS_i/dt = h_i x S_i,  h_i = sum_j (J_ij S_j + D_ij x S_j)
+ *                                 - 2 A S_i^z z - H_z z,
+ * with classical RK4 (no renormalisation) in FP32 and write frames
+ * [n_frames][n_sites][3] fp32 into frames_dev (frame 0 = initial state,
+ * frame f = after f steps).
  *  positions_host : [n_sites][3] fp32 host; neighbour bonds come from them.
  * Initial states: Philox4x32-10 with key = seed, counter = (site low 32 bits,
  * 0, site high 32 bits, 0); u = (word >> 8) * 2^-24; UNIFORM uses z = 2u0 - 1,

@@ -325,6 +325,8 @@ struct TrajArgs {
     int z_max;                 // neighbours per site (ELL width)
     const int32_t* nbr;        // [n][z_max], -1 = none
     const float* jval;         // [n][z_max]
+    const float* dvec;         // [n][z_max][3] DMI vectors D_ij, or null
+    float aniso2, hz;          // 2 A and H_z of Eq. (1)
     float dt;
     int init, pad;
     double sigma;

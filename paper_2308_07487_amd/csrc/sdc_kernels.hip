@@ -1269,7 +1269,8 @@ __global__ void traj_init_kernel(TrajArgs a, float* S) {
     a.frames[3 * i + 2] = (float)z;
 }
 
-// One RK4 stage: k = (sum_j J_ij X_j) x X_i.
+// One RK4 stage: k = h_i x X_i with the effective field of Eq. (1),
+// h_i = sum_j (J_ij X_j + D_ij x X_j) - 2 A X_i^z z - H_z z.
 //  stage 0: acc = k;      Tout = S + dt/2 k
 //  stage 1: acc += 2k;    Tout = S + dt/2 k
 //  stage 2: acc += 2k;    Tout = S + dt k
@@ -1284,11 +1285,19 @@ __global__ __launch_bounds__(256) void traj_stage_kernel(TrajArgs a, int stage, 
         const int32_t j = a.nbr[i * a.z_max + e];
         if (j < 0) continue;
         const float J = a.jval[i * a.z_max + e];
-        h0 += J * X[3 * (int64_t)j];
-        h1 += J * X[3 * (int64_t)j + 1];
-        h2 += J * X[3 * (int64_t)j + 2];
+        const float y0 = X[3 * (int64_t)j], y1 = X[3 * (int64_t)j + 1], y2 = X[3 * (int64_t)j + 2];
+        h0 += J * y0;
+        h1 += J * y1;
+        h2 += J * y2;
+        if (a.dvec) {
+            const float* d = a.dvec + 3 * (i * a.z_max + e);
+            h0 += d[1] * y2 - d[2] * y1;
+            h1 += d[2] * y0 - d[0] * y2;
+            h2 += d[0] * y1 - d[1] * y0;
+        }
     }
     const float x0 = X[3 * i], x1 = X[3 * i + 1], x2 = X[3 * i + 2];
+    h2 += -a.aniso2 * x2 - a.hz;
     const float k0 = h1 * x2 - h2 * x1;
     const float k1 = h2 * x0 - h0 * x2;
     const float k2 = h0 * x1 - h1 * x0;

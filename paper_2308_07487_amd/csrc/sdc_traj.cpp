@@ -1,6 +1,6 @@
 // Trajectory generator entry point: bond tables on the host (nearest
 // neighbours of sc/bcc lattices, or J(r) pairs within a cutoff for open
-// samples), then the RK4 kernels of sdc_kernels.hip.
+// samples, with their DMI vectors), then the RK4 kernels of sdc_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +32,7 @@ struct Bonds {
     int z = 0;
     std::vector<int32_t> nbr;
     std::vector<float> jv;
+    std::vector<float> dv;  // [n][z][3] D (r_j - r_i)/|r_j - r_i|, filled when D != 0
 };
 
 sdc_status lattice_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, Bonds* b, std::string* err) {
@@ -86,6 +87,7 @@ sdc_status lattice_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, B
     b->z = (int)deltas.size();
     b->nbr.resize((size_t)n * b->z);
     b->jv.resize((size_t)n * b->z);
+    if (sp->D != 0.0) b->dv.resize((size_t)n * b->z * 3);
     for (int64_t i = 0; i < n; ++i)
         for (int e = 0; e < b->z; ++e) {
             const int64_t d[3] = {D[3 * i] + deltas[e][0], D[3 * i + 1] + deltas[e][1], D[3 * i + 2] + deltas[e][2]};
@@ -99,6 +101,12 @@ sdc_status lattice_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, B
             float J = (float)sp->J;
             if (sp->coupling == SDC_COUPLING_NN_RANDOM_SIGN) J = (float)std::fabs(sp->J) * bond_sign(sp->seed, i, j);
             b->jv[i * b->z + e] = J;
+            if (!b->dv.empty()) {
+                // unit bond vector from the doubled-coordinate step (minimal image)
+                const double len = std::sqrt((double)(deltas[e][0] * deltas[e][0] + deltas[e][1] * deltas[e][1] +
+                                                      deltas[e][2] * deltas[e][2]));
+                for (int c = 0; c < 3; ++c) b->dv[(i * b->z + e) * 3 + c] = (float)(sp->D * deltas[e][c] / len);
+            }
         }
     return SDC_OK;
 }
@@ -156,11 +164,23 @@ sdc_status cutoff_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, Bo
     b->z = (int)std::max<size_t>(zmax, 1);
     b->nbr.assign((size_t)n * b->z, -1);
     b->jv.assign((size_t)n * b->z, 0.0f);
+    if (sp->D != 0.0) b->dv.assign((size_t)n * b->z * 3, 0.0f);
     for (int64_t i = 0; i < n; ++i) {
         std::sort(nb[i].begin(), nb[i].end());
         for (size_t e = 0; e < nb[i].size(); ++e) {
-            b->nbr[i * b->z + e] = nb[i][e].first;
+            const int64_t j = nb[i][e].first;
+            b->nbr[i * b->z + e] = (int32_t)j;
             b->jv[i * b->z + e] = nb[i][e].second;
+            if (!b->dv.empty()) {
+                double d[3], len2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    d[c] = (double)pos[3 * j + c] - (double)pos[3 * i + c];
+                    len2 += d[c] * d[c];
+                }
+                const double len = std::sqrt(len2);
+                for (int c = 0; c < 3; ++c)
+                    b->dv[(i * b->z + e) * 3 + c] = len > 0.0 ? (float)(sp->D * d[c] / len) : 0.0f;
+            }
         }
     }
     return SDC_OK;
@@ -177,6 +197,8 @@ extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_s
     if (n_frames < 1) return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "n_frames must be >= 1");
     if (!(spec->dt > 0.0) || !std::isfinite(spec->dt) || !std::isfinite(spec->J))
         return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "dt must be > 0 and J finite");
+    if (!std::isfinite(spec->D) || !std::isfinite(spec->A) || !std::isfinite(spec->Hz))
+        return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "D, A and Hz must be finite");
     if (spec->init < SDC_INIT_UNIFORM || spec->init > SDC_INIT_GIVEN)
         return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "unknown init");
     if (spec->init == SDC_INIT_GIVEN && !spec->init_dev)
@@ -206,13 +228,16 @@ extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_s
     if (hipSetDevice(device) != hipSuccess) return sdc_internal_set_error(SDC_ERR_HIP, "hipSetDevice");
     int32_t* d_nbr = nullptr;
     float* d_j = nullptr;
+    float* d_dv = nullptr;
     float* d_work = nullptr;
     auto cleanup = [&]() {
         if (d_nbr) (void)hipFree(d_nbr);
         if (d_j) (void)hipFree(d_j);
+        if (d_dv) (void)hipFree(d_dv);
         if (d_work) (void)hipFree(d_work);
     };
     if (hipMalloc(&d_nbr, b.nbr.size() * 4) != hipSuccess || hipMalloc(&d_j, b.jv.size() * 4) != hipSuccess ||
+        (!b.dv.empty() && hipMalloc(&d_dv, b.dv.size() * 4) != hipSuccess) ||
         hipMalloc(&d_work, (size_t)12 * n_sites * 4) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
@@ -221,6 +246,7 @@ extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_s
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(d_nbr, b.nbr.data(), b.nbr.size() * 4, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(d_j, b.jv.data(), b.jv.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && d_dv) e = hipMemcpyAsync(d_dv, b.dv.data(), b.dv.size() * 4, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) {
         cleanup();
         return sdc_internal_set_error(SDC_ERR_HIP, hipGetErrorString(e));
@@ -230,6 +256,9 @@ extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_s
     ta.z_max = b.z;
     ta.nbr = d_nbr;
     ta.jval = d_j;
+    ta.dvec = d_dv;
+    ta.aniso2 = (float)(2.0 * spec->A);
+    ta.hz = (float)spec->Hz;
     ta.dt = (float)spec->dt;
     ta.init = spec->init;
     ta.sigma = spec->sigma;

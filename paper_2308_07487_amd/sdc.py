@@ -53,7 +53,8 @@ class TrajSpec(ctypes.Structure):
                 ("coupling", ctypes.c_int32), ("r_cut", ctypes.c_float), ("J", ctypes.c_double),
                 ("dt", ctypes.c_double), ("init", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("init_dev", ctypes.c_void_p)]
+                ("init_dev", ctypes.c_void_p), ("D", ctypes.c_double), ("A", ctypes.c_double),
+                ("Hz", ctypes.c_double)]
 
 
 EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize", "sdc_plan_raw",
@@ -348,8 +349,9 @@ class Batch:
 
 def traj_generate(positions, kind, frames_out, cells=(0, 0, 0), J=1.0, dt=0.01, coupling=0,
                   r_cut=0.0, init=INIT_UNIFORM, sigma=0.0, seed=0, init_state=None, device=0,
-                  stream=None):
-    """LL RK4 frames into frames_out (float32 device tensor [T][N][3])."""
+                  stream=None, D=0.0, A=0.0, Hz=0.0):
+    """LL RK4 frames into frames_out (float32 device tensor [T][N][3]); D, A, Hz:
+    the DMI, anisotropy and field terms of Eq. (1)."""
     pos = np.ascontiguousarray(positions, dtype=np.float32)
     sp = TrajSpec()
     sp.kind = int(kind)
@@ -363,6 +365,7 @@ def traj_generate(positions, kind, frames_out, cells=(0, 0, 0), J=1.0, dt=0.01, 
     sp.sigma = float(sigma)
     sp.seed = int(seed)
     sp.init_dev = _dev_ptr(init_state, "torch.float32").value if init_state is not None else None
+    sp.D, sp.A, sp.Hz = float(D), float(A), float(Hz)
     if tuple(frames_out.shape[1:]) != (pos.shape[0], 3):
         raise ValueError("frames_out must have shape [T][n_sites][3]")
     _check(lib().sdc_traj_generate(_np_ptr(pos), pos.shape[0], ctypes.byref(sp),

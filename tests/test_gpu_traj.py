@@ -156,3 +156,66 @@ def test_rk4_conserves_magnetisation(torch_dev, S):
     M = fr.double().sum(dim=1).cpu().numpy()
     assert np.abs(M - M[0]).max() < 1e-3  # fp32 rounding over 512 sites x 200 steps
     assert np.abs(fr[-1].cpu().numpy() - fr[0].cpu().numpy()).max() > 1e-2
+
+
+def _dmi_lattice(n, kind, D):
+    """D_ij = D (r_j - r_i)/|r_j - r_i| for the neighbour order of _nn_csr."""
+    if kind == "sc":
+        deltas = np.array([(2, 0, 0), (-2, 0, 0), (0, 2, 0), (0, -2, 0), (0, 0, 2), (0, 0, -2)], float)
+    else:
+        deltas = np.array([(sx, sy, sz) for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float)
+    unit = deltas / np.linalg.norm(deltas, axis=1, keepdims=True)
+    return np.tile(D * unit, (n, 1))
+
+
+@pytest.mark.parametrize("kind", ["sc", "bcc", "radial"])
+def test_rk4_full_model_matches_oracle(torch_dev, S, orc, kind):
+    """Eq. (2) with every term of Eq. (1): exchange (random signs on bcc),
+    bulk DMI, anisotropy and field, GPU FP32 against the oracle's FP64."""
+    _say(f"rk4 full model {kind}")
+    D, A, Hz, dt, nf = 0.3, 0.2, 0.4, 0.01, 25
+    if kind == "radial":
+        pos = inputs.ball_positions(250, 3.0, seed=8)
+        row, col, Jv = _cutoff_csr(pos, 1.0, 1.5)
+        rij = pos[col].astype(np.float64) - pos[np.repeat(np.arange(pos.shape[0]), np.diff(row))].astype(np.float64)
+        Dv = D * rij / np.linalg.norm(rij, axis=1, keepdims=True)
+        kw = dict(coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5)
+        bins = S.BINS_RADIAL
+        L = (0, 0, 0)
+    else:
+        L = (4, 3, 5)
+        pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+        seed = 0x5DC00519 if kind == "bcc" else None
+        row, col, Jv = _nn_csr(pos, L, kind, -1.0, sign_seed=seed, orc=orc)
+        Dv = _dmi_lattice(pos.shape[0], kind, D)
+        kw = dict(coupling=S.COUPLING_NN_RANDOM_SIGN if seed else S.COUPLING_NN_UNIFORM, seed=seed or 0)
+        bins = S.BINS_SC if kind == "sc" else S.BINS_BCC
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=19)[0]
+    fr = torch_dev.zeros((nf, n, 3), device="cuda")
+    S.traj_generate(pos, bins, fr, cells=L, J=-1.0 if kind != "radial" else 1.0, dt=dt, D=D, A=A, Hz=Hz,
+                    init=S.INIT_GIVEN, init_state=torch_dev.from_numpy(init).cuda(), **kw)
+    ref = orc.ll_rk4(row, col, Jv, init, dt, nf, D=Dv, A=A, Hz=Hz)
+    ref0 = orc.ll_rk4(row, col, Jv, init, dt, nf)  # without the extra terms
+    err = np.abs(fr.cpu().numpy() - ref).max()
+    print(f"  max error {err:.2e} (terms move the state by {np.abs(ref - ref0).max():.2e})", flush=True)
+    assert err < 5e-6 and np.abs(ref - ref0).max() > 1e-2
+
+
+def test_rk4_cone_wave_full_model_exact(torch_dev, S):
+    """Cone spin wave along z on sc with DMI, anisotropy and field: exact
+    solution with w = cos th [J (gamma_q - 6) - 2 D sin q + 2 A] + H_z."""
+    _say("rk4 cone wave, full model")
+    L = (4, 4, 16)
+    pos = inputs.sc_positions(L)
+    J, D, A, Hz, theta, dt, nf = -1.0, 0.35, 0.25, 0.5, 0.6, 0.01, 301
+    q = 2 * np.pi * 3 / L[2]
+    w = np.cos(theta) * (J * (4 + 2 * np.cos(q) - 6) - 2 * D * np.sin(q) + 2 * A) + Hz
+    qv = np.array([0.0, 0.0, q])
+    exact = inputs.spiral_frames(pos, qv, theta, w, nf, dt)
+    fr = torch_dev.zeros((nf, pos.shape[0], 3), device="cuda")
+    S.traj_generate(pos, S.BINS_SC, fr, cells=L, J=J, dt=dt, D=D, A=A, Hz=Hz, init=S.INIT_GIVEN,
+                    init_state=torch_dev.from_numpy(exact[0].copy()).cuda())
+    err = np.abs(fr.cpu().numpy() - exact).max()
+    print(f"  max error {err:.2e}", flush=True)
+    assert err < 3e-5

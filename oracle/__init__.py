@@ -24,6 +24,10 @@ Each function states the paper passage it follows (arXiv 2308.07487):
 - ``ll_rk4``           Eq. (2) with the Hamiltonian of Eq. (1) (exchange, DMI,
                        single-ion anisotropy, field), RK4 without
                        renormalisation (Sec. 3.1).
+- ``mc_anneal``        Metropolis Monte Carlo with a cone of trial moves
+                       adapted to the acceptance rate (Sec. 2.1) and
+                       simulated annealing (Sec. 4.3) on the Hamiltonian of
+                       Eq. (1); greedy colour classes updated in turn.
 - ``philox`` / ``init_state``  Philox4x32-10 (Salmon et al., SC'11) seeded
                        initial states.
 """
@@ -81,13 +85,16 @@ def lib():
         L.oracle_finalize.argtypes = [P, P, i64, i32, i64, P, P, P, P, P, P, P]
         L.oracle_ll_rk4.argtypes = [i64, P, P, P, P, f64, i64, P]
         L.oracle_ll_rk4_full.argtypes = [i64, P, P, P, P, f64, f64, P, f64, i64, P]
+        L.oracle_mc_n_sweeps.argtypes = [f64, f64, f64, i64, i64, P]
+        L.oracle_mc_anneal.argtypes = [i64, P, P, P, P, f64, f64, u64, f64, f64, f64, i64, i64, f64, f64,
+                                       P, P, P, P]
         L.oracle_philox.argtypes = [u64, u32, i64, i64, P]
         L.oracle_init_state.argtypes = [u64, i64, ctypes.c_int, f64, P]
         L.oracle_philox_block.argtypes = [P, P, P]
         for name in ("oracle_n_bins", "oracle_pair_keys", "oracle_binned_corr",
                      "oracle_binned_corr_select", "oracle_self_corr", "oracle_dft",
                      "oracle_finalize", "oracle_ll_rk4", "oracle_ll_rk4_full", "oracle_philox",
-                     "oracle_init_state",
+                     "oracle_init_state", "oracle_mc_n_sweeps", "oracle_mc_anneal",
                      "oracle_philox_block", "oracle_mean_product", "oracle_self_mean_product"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -302,6 +309,41 @@ def ll_rk4(row, col, J, init, dt, n_frames, D=None, A=0.0, Hz=0.0):
     _check(lib().oracle_ll_rk4_full(n, _ptr(row), _ptr(col), _ptr(J), Dp, float(A), float(Hz), _ptr(init),
                                     float(dt), int(n_frames), _ptr(out)), "ll_rk4")
     return out
+
+
+def mc_n_sweeps(T_start, T_end, cool, sweeps_per_T, sweeps_final):
+    """Sweeps of the annealing schedule (T_k = T_start cool^k while T_k > T_end,
+    sweeps_per_T each, then sweeps_final at T_end)."""
+    n = ctypes.c_int64()
+    _check(lib().oracle_mc_n_sweeps(float(T_start), float(T_end), float(cool), int(sweeps_per_T),
+                                    int(sweeps_final), ctypes.byref(n)), "mc_n_sweeps")
+    return int(n.value)
+
+
+def mc_anneal(row, col, J, init, seed, T_start, T_end, cool, sweeps_per_T, sweeps_final,
+              cone0=np.pi, acc_target=0.2, D=None, A=0.0, Hz=0.0):
+    """Annealed Metropolis sweeps with an adaptive cone (Sec. 2.1, Sec. 4.3) on
+    CSR bonds with the Hamiltonian of Eq. (1).  Returns (state [n][3] FP64,
+    accepted moves per sweep, energy per site, final cone, last T, colours)."""
+    row = np.ascontiguousarray(row, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    init = np.ascontiguousarray(init, dtype=np.float32)
+    n = init.shape[0]
+    ns = mc_n_sweeps(T_start, T_end, cool, sweeps_per_T, sweeps_final)
+    state = np.zeros((n, 3))
+    acc = np.zeros(max(ns, 1), dtype=np.int64)
+    info = np.zeros(4)
+    Dp = None
+    if D is not None:
+        D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1, 3)
+        assert D.shape[0] == col.shape[0]
+        Dp = _ptr(D)
+    _check(lib().oracle_mc_anneal(n, _ptr(row), _ptr(col), _ptr(J), Dp, float(A), float(Hz), int(seed),
+                                  float(T_start), float(T_end), float(cool), int(sweeps_per_T),
+                                  int(sweeps_final), float(cone0), float(acc_target), _ptr(init),
+                                  _ptr(state), _ptr(acc), _ptr(info)), "mc_anneal")
+    return state, acc[:ns], float(info[0]), float(info[1]), float(info[2]), int(info[3])
 
 
 def philox(seed, draw, idx0, n_blocks):

@@ -721,3 +721,183 @@ int oracle_init_state(uint64_t seed, int64_t n, int mode, double sigma, double *
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Metropolis Monte Carlo with an adaptive cone and simulated annealing     */
+/* (Sec. 2.1: trial moves in a cone around the spin, Metropolis acceptance, */
+/* cone adapted to keep the acceptance rate near a target; Sec. 4.3:        */
+/* annealing T_{k+1} = cool T_k down to the target temperature)             */
+/* ------------------------------------------------------------------------ */
+
+/* Sweeps of the schedule: temperatures T_k = T_start cool^k (k = 0, 1, ...)
+ * while T_k > T_end, sweeps_per_T sweeps each, then sweeps_final at T_end. */
+static int64_t omc_schedule(double T_start, double T_end, double cool, int64_t sweeps_per_T,
+                            int64_t sweeps_final, double *T_of, int64_t cap) {
+    int64_t s = 0;
+    for (double T = T_start; T > T_end; T *= cool)
+        for (int64_t k = 0; k < sweeps_per_T; ++k) {
+            if (T_of && s < cap) T_of[s] = T;
+            ++s;
+        }
+    for (int64_t k = 0; k < sweeps_final; ++k) {
+        if (T_of && s < cap) T_of[s] = T_end;
+        ++s;
+    }
+    return s;
+}
+
+int oracle_mc_n_sweeps(double T_start, double T_end, double cool, int64_t sweeps_per_T,
+                       int64_t sweeps_final, int64_t *n_sweeps) {
+    if (!(cool > 0.0 && cool < 1.0) || !(T_end > 0.0) || sweeps_per_T < 1 || sweeps_final < 0)
+        return OR_EINVAL;
+    *n_sweeps = omc_schedule(T_start, T_end, cool, sweeps_per_T, sweeps_final, NULL, 0);
+    return OR_OK;
+}
+
+/* Greedy colouring in site order: each site takes the smallest colour that no
+ * lower-indexed neighbour has.  Sites of one colour share no bond. */
+static int32_t ocolour(int64_t n, const int64_t *row, const int32_t *col, int32_t *colour) {
+    int32_t n_col = 0;
+    for (int64_t i = 0; i < n; ++i) colour[i] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c = 0;
+        for (;;) {
+            int used = 0;
+            for (int64_t e = row[i]; e < row[i + 1]; ++e)
+                if (col[e] < i && colour[col[e]] == c) used = 1;
+            if (!used) break;
+            ++c;
+        }
+        colour[i] = c;
+        if (c + 1 > n_col) n_col = c + 1;
+    }
+    return n_col;
+}
+
+/* Local energy of site i in state x (Eq. (1)): x.w - A x_z^2 - Hz x_z, with
+ * w = sum_j (J_ij S_j + D_ij x S_j) the field of the neighbours. */
+static void ofield(int64_t i, const int64_t *row, const int32_t *col, const double *J, const double *Dv,
+                   const double *S, double w[3]) {
+    w[0] = w[1] = w[2] = 0.0;
+    for (int64_t e = row[i]; e < row[i + 1]; ++e) {
+        const double *sj = S + 3 * (int64_t)col[e];
+        w[0] += J[e] * sj[0];
+        w[1] += J[e] * sj[1];
+        w[2] += J[e] * sj[2];
+        if (Dv) {
+            const double *d = Dv + 3 * e;
+            w[0] += d[1] * sj[2] - d[2] * sj[1];
+            w[1] += d[2] * sj[0] - d[0] * sj[2];
+            w[2] += d[0] * sj[1] - d[1] * sj[0];
+        }
+    }
+}
+
+/*
+ * Annealed Metropolis sweeps on the bonds (row, col, J, Dv) with anisotropy
+ * A and field Hz.  Sweep s updates the colour classes in order; site i draws
+ * one Philox4x32-10 block, key = seed, counter = (i low, s low, i high,
+ * 2^31 | s high): u_k = (word_k + 1/2) 2^-32.  Trial spin: cos a = 1 - u_0
+ * (1 - cos cone), azimuth 2 pi u_1 about the current spin, in the frame
+ * e1 = normalised (a - (a.S) S) with a = z (or x when |S_z| >= 0.9),
+ * e2 = S x e1; the trial is renormalised.  Accepted when dE <= 0 or
+ * u_2 < exp(-dE / T).  After each sweep, rate = accepted / n: cone *= 0.9
+ * (not below 1e-3) when rate < acc_target, cone = min(pi, 1.1 cone) when
+ * rate > 2 acc_target.
+ * init: [n][3] fp32; state_out: [n][3] fp64; accepted_out: [n_sweeps] or
+ * NULL; info_out[4]: energy per site (Eq. (1)), final cone, last T, colours.
+ */
+int oracle_mc_anneal(int64_t n, const int64_t *row, const int32_t *col, const double *J,
+                     const double *Dv, double A, double Hz, uint64_t seed, double T_start,
+                     double T_end, double cool, int64_t sweeps_per_T, int64_t sweeps_final,
+                     double cone0, double acc_target, const float *init, double *state_out,
+                     int64_t *accepted_out, double *info_out) {
+    const double pi = 3.14159265358979323846;
+    if (n <= 0 || !(cone0 > 0.0 && cone0 <= pi)) return OR_EINVAL;
+    int64_t n_sweeps = 0;
+    int rc = oracle_mc_n_sweeps(T_start, T_end, cool, sweeps_per_T, sweeps_final, &n_sweeps);
+    if (rc != OR_OK) return rc;
+    double *T_of = (double *)malloc(sizeof(double) * (size_t)(n_sweeps > 0 ? n_sweeps : 1));
+    int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!T_of || !colour) {
+        free(T_of); free(colour);
+        return OR_ENOMEM;
+    }
+    omc_schedule(T_start, T_end, cool, sweeps_per_T, sweeps_final, T_of, n_sweeps);
+    const int32_t n_col = ocolour(n, row, col, colour);
+    double *S = state_out;
+    for (int64_t x = 0; x < 3 * n; ++x) S[x] = (double)init[x];
+    double cone = cone0;
+    double T = T_start;
+    for (int64_t s = 0; s < n_sweeps; ++s) {
+        T = T_of[s];
+        const double cosc = cos(cone);
+        int64_t acc = 0;
+        for (int32_t c = 0; c < n_col; ++c)
+            for (int64_t i = 0; i < n; ++i) {
+                if (colour[i] != c) continue;
+                uint32_t ctr[4] = {(uint32_t)i, (uint32_t)s, (uint32_t)((uint64_t)i >> 32),
+                                   0x80000000u | (uint32_t)((uint64_t)s >> 32)};
+                ophilox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+                const double u0 = ((double)ctr[0] + 0.5) * (1.0 / 4294967296.0);
+                const double u1 = ((double)ctr[1] + 0.5) * (1.0 / 4294967296.0);
+                const double u2 = ((double)ctr[2] + 0.5) * (1.0 / 4294967296.0);
+                double *si = S + 3 * i;
+                const double cosa = 1.0 - u0 * (1.0 - cosc);
+                const double sina = sqrt(fmax(0.0, 1.0 - cosa * cosa));
+                const double cb = cos(2.0 * pi * u1), sb = sin(2.0 * pi * u1);
+                double a[3] = {0.0, 0.0, 1.0};
+                if (fabs(si[2]) >= 0.9) { a[0] = 1.0; a[2] = 0.0; }
+                const double as = a[0] * si[0] + a[1] * si[1] + a[2] * si[2];
+                double e1[3] = {a[0] - as * si[0], a[1] - as * si[1], a[2] - as * si[2]};
+                const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+                e1[0] /= l1; e1[1] /= l1; e1[2] /= l1;
+                const double e2[3] = {si[1] * e1[2] - si[2] * e1[1], si[2] * e1[0] - si[0] * e1[2],
+                                      si[0] * e1[1] - si[1] * e1[0]};
+                double t[3];
+                for (int k = 0; k < 3; ++k) t[k] = cosa * si[k] + sina * (cb * e1[k] + sb * e2[k]);
+                const double lt = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+                t[0] /= lt; t[1] /= lt; t[2] /= lt;
+                double w[3];
+                ofield(i, row, col, J, Dv, S, w);
+                const double dE = ((t[0] - si[0]) * w[0] + (t[1] - si[1]) * w[1] + (t[2] - si[2]) * w[2])
+                                  - A * (t[2] * t[2] - si[2] * si[2]) - Hz * (t[2] - si[2]);
+                if (dE <= 0.0 || u2 < exp(-dE / T)) {
+                    si[0] = t[0]; si[1] = t[1]; si[2] = t[2];
+                    ++acc;
+                }
+            }
+        if (accepted_out) accepted_out[s] = acc;
+        const double rate = (double)acc / (double)n;
+        if (rate < acc_target) cone = fmax(1e-3, 0.9 * cone);
+        else if (rate > 2.0 * acc_target) cone = fmin(pi, 1.1 * cone);
+    }
+    /* energy per site: half of each site's bond energies (every bond seen
+     * from both ends) plus its single-site terms */
+    double E = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *si = S + 3 * i;
+        double eb = 0.0;
+        for (int64_t e = row[i]; e < row[i + 1]; ++e) {
+            const double *sj = S + 3 * (int64_t)col[e];
+            eb += J[e] * (si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2]);
+            if (Dv) {
+                const double *d = Dv + 3 * e;
+                const double cx = si[1] * sj[2] - si[2] * sj[1];
+                const double cy = si[2] * sj[0] - si[0] * sj[2];
+                const double cz = si[0] * sj[1] - si[1] * sj[0];
+                eb -= d[0] * cx + d[1] * cy + d[2] * cz;
+            }
+        }
+        E += 0.5 * eb - A * si[2] * si[2] - Hz * si[2];
+    }
+    if (info_out) {
+        info_out[0] = E / (double)n;
+        info_out[1] = cone;
+        info_out[2] = T;
+        info_out[3] = (double)n_col;
+    }
+    free(T_of);
+    free(colour);
+    return OR_OK;
+}

@@ -752,3 +752,123 @@ def test_rk4_full_model_conserves_energy(orc):
     for wrong in (dict(D=-Dv, A=A, Hz=Hz), dict(D=Dv, A=-A, Hz=Hz)):
         o2 = orc.ll_rk4(row, col, Jv, init, dt, nf, **wrong)
         assert abs(_energy(o2[-1], row, col, Jv, Dv, A, Hz) - E0) > 1e-4
+
+
+# --------------------------------------------------------------------------
+# Metropolis Monte Carlo with an adaptive cone, simulated annealing
+# --------------------------------------------------------------------------
+
+def _langevin(x):
+    return 1.0 / np.tanh(x) - 1.0 / x
+
+
+def test_mc_independent_spins_field_and_anisotropy(orc):
+    """Spins without bonds in a field H_z and anisotropy A sample
+    p(S_z) ~ exp((A S_z^2 + H_z S_z) / T) on the sphere (S_z uniform under the
+    uniform measure): the mean and second moment of S_z over 20000 spins
+    match the quadrature within 4 standard errors, and the transverse
+    components average to zero."""
+    from scipy.integrate import quad
+    n, T, A, Hz = 20000, 0.5, 0.3, 0.4
+    row = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(0, dtype=np.int32)
+    init = inputs.random_unit_frames(1, n, seed=41)[0]
+    S, acc, E, cone, Tl, ncol = orc.mc_anneal(row, col, np.zeros(0), init, 0x5DC0AA01, T, T, 0.9, 1, 300,
+                                              A=A, Hz=Hz)
+    assert ncol == 1 and Tl == T and acc.shape == (300,)
+    w = lambda x: np.exp((A * x * x + Hz * x) / T)
+    Z = quad(w, -1, 1)[0]
+    m1 = quad(lambda x: x * w(x), -1, 1)[0] / Z
+    m2 = quad(lambda x: x * x * w(x), -1, 1)[0] / Z
+    se = np.sqrt((m2 - m1 * m1) / n)
+    assert abs(S[:, 2].mean() - m1) < 4 * se, (S[:, 2].mean(), m1, se)
+    assert abs((S[:, 2] ** 2).mean() - m2) < 4 * np.sqrt(1.0 / n)
+    assert abs(S[:, 0].mean()) < 4 * np.sqrt(0.5 / n)
+    # the energy per site reported is -A <Sz^2> - Hz <Sz> of this state
+    np.testing.assert_allclose(E, np.mean(-A * S[:, 2] ** 2 - Hz * S[:, 2]), rtol=1e-12)
+
+
+def _pairs(n_pairs, J, D=None):
+    """n_pairs isolated bonds (2k, 2k+1); DMI vector D along +x for (2k, 2k+1)."""
+    row = np.arange(2 * n_pairs + 1, dtype=np.int64)
+    col = np.array([[2 * k + 1, 2 * k] for k in range(n_pairs)], dtype=np.int32).reshape(-1)
+    Jv = np.full(2 * n_pairs, float(J))
+    Dv = None
+    if D is not None:
+        Dv = np.array([[[D, 0.0, 0.0], [-D, 0.0, 0.0]] for _ in range(n_pairs)]).reshape(-1, 3)
+    return row, col, Jv, Dv
+
+
+def test_mc_exchange_pairs(orc):
+    """Isolated bonds J S1.S2 at temperature T: the relative angle has
+    p(cos g) ~ exp(-J cos g / T), so <S1.S2> = -L(J / T) with the Langevin
+    function L(x) = coth x - 1/x; checked for both signs of J."""
+    n_pairs, T = 10000, 0.7
+    for J in (1.0, -1.3):
+        row, col, Jv, _ = _pairs(n_pairs, J)
+        init = inputs.random_unit_frames(1, 2 * n_pairs, seed=42)[0]
+        S, acc, E, *_ = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA02, T, T, 0.9, 1, 300)
+        dots = np.sum(S[0::2] * S[1::2], axis=1)
+        ref = -_langevin(J / T)
+        se = np.sqrt(np.var(dots) / n_pairs)
+        assert abs(dots.mean() - ref) < 4 * se, (J, dots.mean(), ref, se)
+        np.testing.assert_allclose(E, J * dots.mean() / 2.0, rtol=1e-12)
+
+
+def test_mc_dmi_pairs(orc):
+    """Isolated bonds with only DMI, E = -D x.(S1 x S2): given S2 at angle t
+    to x, S1 sees a field of size u = D sin t, so the pair's mean energy is
+    the quadrature of -u L(u/T) weighted by sinh(u/T)/(u/T) over t."""
+    from scipy.integrate import quad
+    n_pairs, T, D = 10000, 0.5, 1.2
+    row, col, Jv, Dv = _pairs(n_pairs, 0.0, D)
+    init = inputs.random_unit_frames(1, 2 * n_pairs, seed=43)[0]
+    S, acc, E, *_ = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA03, T, T, 0.9, 1, 300, D=Dv)
+    e = -D * np.cross(S[0::2], S[1::2])[:, 0]
+    def weight(t):
+        x = max(D * np.sin(t) / T, 1e-12)
+        return np.sinh(x) / x * np.sin(t)
+    def energy(t):
+        u = D * np.sin(t)
+        return -u * _langevin(max(u / T, 1e-12)) * weight(t)
+    ref = quad(energy, 0, np.pi)[0] / quad(weight, 0, np.pi)[0]
+    se = np.sqrt(np.var(e) / n_pairs)
+    assert abs(e.mean() - ref) < 4 * se, (e.mean(), ref, se)
+    np.testing.assert_allclose(E, e.mean() / 2.0, rtol=1e-12)
+
+
+def test_mc_anneal_ferromagnet_ground_state(orc):
+    """Annealing an sc ferromagnet (J = -1) from T = 3 to 0.05 with T_{k+1} =
+    0.9 T_k reaches the aligned state: E/N near -3 (3 bonds per site) and
+    |M|/N near 1; the cone has shrunk and kept the acceptance near its
+    target."""
+    L = (4, 4, 4)
+    pos = inputs.sc_positions(L)
+    row, col, Jv, _ = _nn_csr(pos, L, "sc", -1.0)
+    init = inputs.random_unit_frames(1, pos.shape[0], seed=44)[0]
+    S, acc, E, cone, Tl, ncol = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA04, 3.0, 0.05, 0.9, 20, 100,
+                                              cone0=np.pi)
+    assert ncol == 2 and Tl == 0.05
+    assert -3.0 <= E < -2.9, E
+    assert np.linalg.norm(S.sum(axis=0)) / pos.shape[0] > 0.97
+    assert cone < 1.0
+    rate = acc[-50:].mean() / pos.shape[0]
+    assert 0.1 < rate < 0.6, rate
+
+
+def test_mc_deterministic_and_schedule(orc):
+    """Same seed, same result; the schedule has one block of sweeps per
+    temperature above T_end plus the final sweeps."""
+    assert orc.mc_n_sweeps(1.0, 0.5, 0.5, 3, 4) == 3 + 4  # T = 1 only
+    assert orc.mc_n_sweeps(1.0, 0.2, 0.5, 2, 1) == 3 * 2 + 1  # T = 1, 0.5, 0.25
+    assert orc.mc_n_sweeps(0.1, 0.2, 0.5, 2, 5) == 5  # no annealing stage
+    L = (3, 3, 3)
+    pos = inputs.sc_positions(L)
+    row, col, Jv, _ = _nn_csr(pos, L, "sc", 1.0)
+    init = inputs.random_unit_frames(1, pos.shape[0], seed=45)[0]
+    a = orc.mc_anneal(row, col, Jv, init, 7, 2.0, 0.5, 0.8, 3, 5)
+    b = orc.mc_anneal(row, col, Jv, init, 7, 2.0, 0.5, 0.8, 3, 5)
+    c = orc.mc_anneal(row, col, Jv, init, 8, 2.0, 0.5, 0.8, 3, 5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert not np.array_equal(a[0], c[0])
+    assert a[5] >= 3  # an odd periodic box has no two-colouring

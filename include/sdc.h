@@ -426,7 +426,9 @@ typedef struct {
  *         - H_z sum_i S_i^z,
  *     dS_i/dt = h_i x S_i,  h_i = sum_j (J_ij S_j + D_ij x S_j)
  *                                 - 2 A S_i^z z - H_z z,
- * with classical RK4 (no renormalisation) in FP32 and write frames
+ * (lattice bonds that close on the site itself, along an axis one cell
+ * wide, are dropped) with classical RK4 (no renormalisation) in FP32 and
+ * write frames
  * [n_frames][n_sites][3] fp32 into frames_dev (frame 0 = initial state,
  * frame f = after f steps).
  *  positions_host : [n_sites][3] fp32 host; neighbour bonds come from them.
@@ -441,6 +443,57 @@ typedef struct {
 sdc_status sdc_traj_generate(const float* positions_host, int64_t n_sites,
                              const sdc_traj_spec* spec, float* frames_dev,
                              int64_t n_frames, int device, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Thermalised starts: Metropolis Monte Carlo with simulated annealing     */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t kind;         /* as sdc_traj_spec: SC/BCC nearest neighbours or   */
+    int32_t cells[3];     /* RADIAL with EXP_CUTOFF couplings                 */
+    int32_t coupling;     /* sdc_coupling                                     */
+    float r_cut;          /* EXP_CUTOFF: cutoff radius                        */
+    double J, D, A, Hz;   /* Eq. (1): exchange, bulk DMI, anisotropy, field   */
+    uint64_t seed;        /* Philox key of the moves (and of random bond signs) */
+    double T_start;       /* annealing: T_k = T_start cool^k while T_k > T_end */
+    double T_end;         /* then the final sweeps at T_end (> 0)             */
+    double cool;          /* in (0, 1)                                        */
+    int64_t sweeps_per_T; /* sweeps at each temperature of the ladder (>= 1)  */
+    int64_t sweeps_final; /* sweeps at T_end (>= 0)                           */
+    double cone0;         /* initial trial-cone half-angle, (0, pi]           */
+    double acc_target;    /* acceptance-rate target of the adaptation, (0, 0.5] */
+} sdc_mc_spec;
+
+/* Number of sweeps of the spec's schedule (host only).  Errors: INVALID_ARG. */
+sdc_status sdc_mc_n_sweeps(const sdc_mc_spec* spec, int64_t* n_sweeps);
+
+/*
+ * Thermalised spin configurations by Metropolis Monte Carlo (Sec. 2.1) with
+ * simulated annealing (Sec. 4.3) on the Hamiltonian of Eq. (1), as starts
+ * for sdc_traj_generate (SDC_INIT_GIVEN).  A sweep visits the colour
+ * classes of a greedy colouring of the bond graph (each site takes the
+ * smallest colour no lower-indexed neighbour has) in order, all sites of a
+ * class in parallel.  Site i in sweep s draws one Philox4x32-10 block, key =
+ * seed, counter = (i low, s low, i high, 2^31 | s high), u_k = (w_k + 1/2)
+ * 2^-32: trial spin at cos a = 1 - u_0 (1 - cos cone) and azimuth 2 pi u_1
+ * about S_i (frame e1 = normalised z - (z.S)S, or x when |S_z| >= 0.9,
+ * e2 = S x e1), renormalised; accepted when dE <= 0 or u_2 < exp(-dE/T).
+ * After each sweep, with rate = accepted / N: cone *= 0.9 (not below 1e-3)
+ * if rate < acc_target, cone = min(pi, 1.1 cone) if rate > 2 acc_target.
+ * The state is FP64 on the device.
+ *  positions_host : [n_sites][3] fp32 (bonds as in sdc_traj_generate).
+ *  init_dev       : [n_sites][3] fp32 device start (e.g. a one-frame
+ *                   sdc_traj_generate with a Philox start).
+ *  state_dev      : [n_sites][3] fp32 device output (may equal init_dev).
+ *  accepted_host  : [sdc_mc_n_sweeps] accepted moves per sweep, or NULL.
+ *  info_host      : [4] energy per site (Eq. (1)) of the final state, final
+ *                   cone, last temperature, number of colour classes; or NULL.
+ * Synchronises the stream (allocates and frees its own device memory).
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP, NO_DEVICE.
+ */
+sdc_status sdc_mc_anneal(const float* positions_host, int64_t n_sites, const sdc_mc_spec* spec,
+                         const float* init_dev, float* state_dev, int64_t* accepted_host,
+                         double* info_host, int device, void* stream);
 
 #ifdef __cplusplus
 }

@@ -338,6 +338,29 @@ struct TrajArgs {
 };
 int launch_traj(const TrajArgs& a, void* stream);
 
+// Metropolis sweeps (sdc_mc.hip).
+struct McArgs {
+    int64_t n;
+    int z_max;
+    const int32_t* nbr;        // [n][z_max], -1 = none
+    const float* jval;         // [n][z_max]
+    const float* dvec;         // [n][z_max][3] DMI vectors, or null
+    double A, Hz;              // anisotropy and field of Eq. (1)
+    uint64_t seed;             // Philox key of the moves
+    double acc_target;         // acceptance-rate target of the cone adaptation
+    double* S;                 // [n][3] FP64 state
+    double* cone;              // [2]: cone half-angle, its cosine
+    unsigned long long* accepted;  // accepted moves of the current sweep
+};
+int mc_energy_blocks(int64_t n);
+int launch_mc_setup(const McArgs& a, const float* init, double cone0, void* stream);
+// One sweep: every colour class in order, then the cone update (history[sweep]
+// receives the accepted moves when history is not null).
+int launch_mc_sweep(const McArgs& a, const int32_t* const* class_sites, const int64_t* class_count, int n_classes,
+                    double T, int64_t sweep, long long* history, void* stream);
+// Energy per site, final cone and temperature into info[0..2]; state as fp32.
+int launch_mc_finish(const McArgs& a, double* partial, double T_last, float* out, double* info, void* stream);
+
 int fused_lds_bytes(int win, int precision);
 // Largest dynamic LDS of a fused launch (the CU's 160 KB less room for the
 // batch kernel's few static words) and the self kernel's staging budget.

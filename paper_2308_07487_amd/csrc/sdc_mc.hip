@@ -1,0 +1,206 @@
+// Metropolis Monte Carlo with an adaptive trial cone and simulated annealing
+// (Sec. 2.1, Sec. 4.3) on the Hamiltonian of Eq. (1), on gfx950.
+//
+// Sites are split into colour classes that share no bond (greedy colouring
+// on the host), so one class is updated in parallel, one thread per site.
+// The state is FP64.  Every random number is a Philox4x32-10 draw of the
+// (site, sweep) counter, so a sweep's result does not depend on the order in
+// which threads run; the cone and the acceptance counter live in device
+// memory and are updated by a one-thread kernel after each sweep, so a whole
+// schedule is queued without host round trips.
+#include <hip/hip_runtime.h>
+
+#include "sdc_internal.h"
+
+namespace sdc {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// One colour class of one sweep.  Site i's move: trial spin in a cone of
+// half-angle `cone` about S_i (cos a uniform in [cos cone, 1], azimuth
+// uniform), Metropolis acceptance at temperature T.  Counter = (i low,
+// sweep low, i high, 2^31 | sweep high), key = seed: u_k = (w_k + 1/2) 2^-32.
+__global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, const int32_t* __restrict__ sites, int64_t count,
+                                                        double T, int64_t sweep) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool accepted = false;
+    if (k < count) {
+        const int64_t i = sites[k];
+        // field of the neighbours: sum_j (J_ij S_j + D_ij x S_j)
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+        for (int e = 0; e < a.z_max; ++e) {
+            const int32_t j = a.nbr[i * a.z_max + e];
+            if (j < 0) continue;
+            const double J = a.jval[i * a.z_max + e];
+            const double y0 = a.S[3 * (int64_t)j], y1 = a.S[3 * (int64_t)j + 1], y2 = a.S[3 * (int64_t)j + 2];
+            w0 += J * y0;
+            w1 += J * y1;
+            w2 += J * y2;
+            if (a.dvec) {
+                const float* d = a.dvec + 3 * (i * a.z_max + e);
+                const double d0 = d[0], d1 = d[1], d2 = d[2];
+                w0 += d1 * y2 - d2 * y1;
+                w1 += d2 * y0 - d0 * y2;
+                w2 += d0 * y1 - d1 * y0;
+            }
+        }
+        double* si = a.S + 3 * i;
+        const double s0 = si[0], s1 = si[1], s2 = si[2];
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)sweep, (uint32_t)((uint64_t)i >> 32),
+                         0x80000000u | (uint32_t)((uint64_t)sweep >> 32)};
+        philox4x32_10(c, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        const double u0 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
+        const double u1 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
+        const double u2 = ((double)c[2] + 0.5) * (1.0 / 4294967296.0);
+        const double cosa = 1.0 - u0 * (1.0 - a.cone[1]);
+        const double sina = sqrt(fmax(0.0, 1.0 - cosa * cosa));
+        double sb, cb;
+        sincospi(2.0 * u1, &sb, &cb);
+        // frame about S_i: e1 from z (x when S_i is near z), e2 = S_i x e1
+        const bool near_z = fabs(s2) >= 0.9;
+        const double ax = near_z ? 1.0 : 0.0, az = near_z ? 0.0 : 1.0;
+        const double as = ax * s0 + az * s2;
+        double e10 = ax - as * s0, e11 = -as * s1, e12 = az - as * s2;
+        const double l1 = sqrt(e10 * e10 + e11 * e11 + e12 * e12);
+        e10 /= l1;
+        e11 /= l1;
+        e12 /= l1;
+        const double e20 = s1 * e12 - s2 * e11, e21 = s2 * e10 - s0 * e12, e22 = s0 * e11 - s1 * e10;
+        double t0 = cosa * s0 + sina * (cb * e10 + sb * e20);
+        double t1 = cosa * s1 + sina * (cb * e11 + sb * e21);
+        double t2 = cosa * s2 + sina * (cb * e12 + sb * e22);
+        const double lt = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        t0 /= lt;
+        t1 /= lt;
+        t2 /= lt;
+        const double dE = ((t0 - s0) * w0 + (t1 - s1) * w1 + (t2 - s2) * w2) - a.A * (t2 * t2 - s2 * s2) -
+                          a.Hz * (t2 - s2);
+        if (dE <= 0.0 || u2 < exp(-dE / T)) {
+            si[0] = t0;
+            si[1] = t1;
+            si[2] = t2;
+            accepted = true;
+        }
+    }
+    const unsigned long long ball = __ballot(accepted);
+    if ((threadIdx.x & 63) == 0 && ball != 0ull)
+        atomicAdd(a.accepted, (unsigned long long)__popcll(ball));
+}
+
+// After a sweep: record the accepted moves, adapt the cone, clear the counter.
+__global__ void mc_cone_kernel(McArgs a, long long* history, int64_t sweep) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long acc = *a.accepted;
+    if (history) history[sweep] = (long long)acc;
+    const double rate = (double)acc / (double)a.n;
+    double c = a.cone[0];
+    if (rate < a.acc_target)
+        c = fmax(1e-3, 0.9 * c);
+    else if (rate > 2.0 * a.acc_target)
+        c = fmin(kPi, 1.1 * c);
+    a.cone[0] = c;
+    a.cone[1] = cos(c);
+    *a.accepted = 0ull;
+}
+
+__global__ void mc_setup_kernel(McArgs a, double cone0) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    a.cone[0] = cone0;
+    a.cone[1] = cos(cone0);
+    *a.accepted = 0ull;
+}
+
+__global__ __launch_bounds__(256) void mc_load_kernel(McArgs a, const float* __restrict__ init) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * a.n; x += (int64_t)gridDim.x * blockDim.x)
+        a.S[x] = (double)init[x];
+}
+
+// Energy of Eq. (1) per block: half of each site's bond energies (each bond
+// is seen from both ends) plus its single-site terms; partial sums per block.
+__global__ __launch_bounds__(256) void mc_energy_kernel(McArgs a, double* __restrict__ partial) {
+    __shared__ double red[256];
+    double e = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double* si = a.S + 3 * i;
+        double eb = 0.0;
+        for (int k = 0; k < a.z_max; ++k) {
+            const int32_t j = a.nbr[i * a.z_max + k];
+            if (j < 0) continue;
+            const double* sj = a.S + 3 * (int64_t)j;
+            eb += (double)a.jval[i * a.z_max + k] * (si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2]);
+            if (a.dvec) {
+                const float* d = a.dvec + 3 * (i * a.z_max + k);
+                const double cx = si[1] * sj[2] - si[2] * sj[1];
+                const double cy = si[2] * sj[0] - si[0] * sj[2];
+                const double cz = si[0] * sj[1] - si[1] * sj[0];
+                eb -= (double)d[0] * cx + (double)d[1] * cy + (double)d[2] * cz;
+            }
+        }
+        e += 0.5 * eb - a.A * si[2] * si[2] - a.Hz * si[2];
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Final state as fp32 and the info block: energy per site (partials summed
+// in block order), cone, last temperature.
+__global__ __launch_bounds__(256) void mc_out_kernel(McArgs a, float* __restrict__ out) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * a.n; x += (int64_t)gridDim.x * blockDim.x)
+        out[x] = (float)a.S[x];
+}
+
+__global__ void mc_info_kernel(McArgs a, const double* __restrict__ partial, int n_partial, double T_last,
+                               double* __restrict__ info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double e = 0.0;
+    for (int b = 0; b < n_partial; ++b) e += partial[b];
+    info[0] = e / (double)a.n;
+    info[1] = a.cone[0];
+    info[2] = T_last;
+}
+
+unsigned grid_of(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+int mc_energy_blocks(int64_t n) { return (int)grid_of(n); }
+
+int launch_mc_setup(const McArgs& a, const float* init, double cone0, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(mc_load_kernel, dim3(grid_of(3 * a.n)), dim3(256), 0, s, a, init);
+    hipLaunchKernelGGL(mc_setup_kernel, dim3(1), dim3(64), 0, s, a, cone0);
+    return (int)hipGetLastError();
+}
+
+int launch_mc_sweep(const McArgs& a, const int32_t* const* class_sites, const int64_t* class_count, int n_classes,
+                    double T, int64_t sweep, long long* history, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    for (int c = 0; c < n_classes; ++c) {
+        if (class_count[c] == 0) continue;
+        const unsigned grid = (unsigned)((class_count[c] + 255) / 256);
+        hipLaunchKernelGGL(mc_colour_kernel, dim3(grid), dim3(256), 0, s, a, class_sites[c], class_count[c], T, sweep);
+    }
+    hipLaunchKernelGGL(mc_cone_kernel, dim3(1), dim3(64), 0, s, a, history, sweep);
+    return (int)hipGetLastError();
+}
+
+int launch_mc_finish(const McArgs& a, double* partial, double T_last, float* out, double* info, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned g = grid_of(a.n);
+    hipLaunchKernelGGL(mc_energy_kernel, dim3(g), dim3(256), 0, s, a, partial);
+    hipLaunchKernelGGL(mc_out_kernel, dim3(grid_of(3 * a.n)), dim3(256), 0, s, a, out);
+    hipLaunchKernelGGL(mc_info_kernel, dim3(1), dim3(64), 0, s, a, (const double*)partial, (int)g, T_last, info);
+    return (int)hipGetLastError();
+}
+
+}  // namespace sdc

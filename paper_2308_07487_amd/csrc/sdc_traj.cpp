@@ -97,6 +97,11 @@ sdc_status lattice_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, B
                 return SDC_ERR_INVALID_ARG;
             }
             const int64_t j = it->second;
+            if (j == i) {  // a box one cell wide: the bond closes on the site itself and is dropped
+                b->nbr[i * b->z + e] = -1;
+                b->jv[i * b->z + e] = 0.0f;
+                continue;
+            }
             b->nbr[i * b->z + e] = (int32_t)j;
             float J = (float)sp->J;
             if (sp->coupling == SDC_COUPLING_NN_RANDOM_SIGN) J = (float)std::fabs(sp->J) * bond_sign(sp->seed, i, j);
@@ -186,6 +191,51 @@ sdc_status cutoff_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, Bo
     return SDC_OK;
 }
 
+sdc_status build_bonds(const float* pos, int64_t n, const sdc_traj_spec* sp, Bonds* b, std::string* err) {
+    try {
+        if ((sp->kind == SDC_BINS_PERIODIC_SC || sp->kind == SDC_BINS_PERIODIC_BCC) &&
+            (sp->coupling == SDC_COUPLING_NN_UNIFORM || sp->coupling == SDC_COUPLING_NN_RANDOM_SIGN))
+            return lattice_bonds(pos, n, sp, b, err);
+        if (sp->kind == SDC_BINS_RADIAL && sp->coupling == SDC_COUPLING_EXP_CUTOFF) return cutoff_bonds(pos, n, sp, b, err);
+    } catch (const std::bad_alloc&) {
+        *err = "host allocation failed";
+        return SDC_ERR_OOM;
+    }
+    *err = "unsupported kind/coupling combination";
+    return SDC_ERR_UNSUPPORTED;
+}
+
+// The annealing schedule: T_k = T_start cool^k while T_k > T_end,
+// sweeps_per_T sweeps each, then sweeps_final sweeps at T_end.  Calls
+// visit(T) once per sweep, in order; returns the number of sweeps.
+template <class F>
+int64_t mc_schedule(const sdc_mc_spec* m, F visit) {
+    int64_t s = 0;
+    for (double T = m->T_start; T > m->T_end; T *= m->cool)
+        for (int64_t k = 0; k < m->sweeps_per_T; ++k, ++s) visit(T);
+    for (int64_t k = 0; k < m->sweeps_final; ++k, ++s) visit(m->T_end);
+    return s;
+}
+
+sdc_status mc_check(const sdc_mc_spec* m) {
+    const double pi = 3.14159265358979323846;
+    if (!std::isfinite(m->J) || !std::isfinite(m->D) || !std::isfinite(m->A) || !std::isfinite(m->Hz))
+        return sdc::set_error(SDC_ERR_INVALID_ARG, "J, D, A and Hz must be finite");
+    if (!(m->T_end > 0.0) || !std::isfinite(m->T_end) || !(m->T_start > 0.0) || !std::isfinite(m->T_start))
+        return sdc::set_error(SDC_ERR_INVALID_ARG, "temperatures must be finite and > 0");
+    if (!(m->cool > 0.0 && m->cool < 1.0)) return sdc::set_error(SDC_ERR_INVALID_ARG, "cool must be in (0, 1)");
+    if (m->sweeps_per_T < 1 || m->sweeps_final < 0)
+        return sdc::set_error(SDC_ERR_INVALID_ARG, "sweeps_per_T must be >= 1 and sweeps_final >= 0");
+    if (!(m->cone0 > 0.0 && m->cone0 <= pi)) return sdc::set_error(SDC_ERR_INVALID_ARG, "cone0 must be in (0, pi]");
+    if (!(m->acc_target > 0.0 && m->acc_target <= 0.5))
+        return sdc::set_error(SDC_ERR_INVALID_ARG, "acc_target must be in (0, 0.5]");
+    // at most 2^40 sweeps (the ladder has log(T_end / T_start) / log(cool) rungs)
+    const double rungs = m->T_start > m->T_end ? std::ceil(std::log(m->T_end / m->T_start) / std::log(m->cool)) + 1 : 0;
+    if (rungs * (double)m->sweeps_per_T + (double)m->sweeps_final > 1099511627776.0)
+        return sdc::set_error(SDC_ERR_UNSUPPORTED, "schedule longer than 2^40 sweeps");
+    return SDC_OK;
+}
+
 }  // namespace
 
 extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_sites, const sdc_traj_spec* spec,
@@ -207,18 +257,7 @@ extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_s
         return sdc_internal_set_error(SDC_ERR_INVALID_ARG, "sigma must be >= 0");
     Bonds b;
     std::string err;
-    sdc_status s;
-    try {
-        if ((spec->kind == SDC_BINS_PERIODIC_SC || spec->kind == SDC_BINS_PERIODIC_BCC) &&
-            (spec->coupling == SDC_COUPLING_NN_UNIFORM || spec->coupling == SDC_COUPLING_NN_RANDOM_SIGN))
-            s = lattice_bonds(positions_host, n_sites, spec, &b, &err);
-        else if (spec->kind == SDC_BINS_RADIAL && spec->coupling == SDC_COUPLING_EXP_CUTOFF)
-            s = cutoff_bonds(positions_host, n_sites, spec, &b, &err);
-        else
-            return sdc_internal_set_error(SDC_ERR_UNSUPPORTED, "unsupported kind/coupling combination");
-    } catch (const std::bad_alloc&) {
-        return sdc_internal_set_error(SDC_ERR_OOM, "host allocation failed");
-    }
+    const sdc_status s = build_bonds(positions_host, n_sites, spec, &b, &err);
     if (s != SDC_OK) return sdc_internal_set_error(s, err.c_str());
 
     int count = 0;
@@ -273,4 +312,141 @@ extern "C" sdc_status sdc_traj_generate(const float* positions_host, int64_t n_s
     if (le != 0) return sdc_internal_set_error(SDC_ERR_HIP, hipGetErrorString((hipError_t)le));
     if (se != hipSuccess) return sdc_internal_set_error(SDC_ERR_HIP, hipGetErrorString(se));
     return sdc_internal_set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_n_sweeps(const sdc_mc_spec* spec, int64_t* n_sweeps) {
+    if (!spec || !n_sweeps) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    const sdc_status s = mc_check(spec);
+    if (s != SDC_OK) return s;
+    *n_sweeps = mc_schedule(spec, [](double) {});
+    return sdc::set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_anneal(const float* positions_host, int64_t n_sites, const sdc_mc_spec* spec,
+                                    const float* init_dev, float* state_dev, int64_t* accepted_host,
+                                    double* info_host, int device, void* stream) {
+    if (!positions_host || !spec || !init_dev || !state_dev) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    if (n_sites < 1 || n_sites > ((int64_t)1 << 26)) return sdc::set_error(SDC_ERR_INVALID_ARG, "n_sites out of range");
+    sdc_status s = mc_check(spec);
+    if (s != SDC_OK) return s;
+    sdc_traj_spec ts{};
+    ts.kind = spec->kind;
+    for (int a = 0; a < 3; ++a) ts.cells[a] = spec->cells[a];
+    ts.coupling = spec->coupling;
+    ts.r_cut = spec->r_cut;
+    ts.J = spec->J;
+    ts.D = spec->D;
+    ts.seed = spec->seed;
+    Bonds b;
+    std::string err;
+    s = build_bonds(positions_host, n_sites, &ts, &b, &err);
+    if (s != SDC_OK) return sdc::set_error(s, err);
+    // greedy colouring in site order, then the sites grouped by colour
+    std::vector<int32_t> colour((size_t)n_sites, -1);
+    int n_col = 0;
+    std::vector<char> used;
+    for (int64_t i = 0; i < n_sites; ++i) {
+        used.assign((size_t)n_col + 1, 0);
+        for (int e = 0; e < b.z; ++e) {
+            const int32_t j = b.nbr[i * b.z + e];
+            if (j >= 0 && j < i) used[(size_t)colour[j]] = 1;
+        }
+        int c = 0;
+        while (used[(size_t)c]) ++c;
+        colour[i] = c;
+        n_col = std::max(n_col, c + 1);
+    }
+    std::vector<int64_t> count((size_t)n_col, 0), start((size_t)n_col + 1, 0);
+    for (int64_t i = 0; i < n_sites; ++i) ++count[(size_t)colour[i]];
+    for (int c = 0; c < n_col; ++c) start[(size_t)c + 1] = start[(size_t)c] + count[(size_t)c];
+    std::vector<int32_t> order((size_t)n_sites);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n_sites; ++i) order[(size_t)fill[(size_t)colour[i]]++] = (int32_t)i;
+    }
+    const int64_t n_sweeps = mc_schedule(spec, [](double) {});
+
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
+        return sdc::set_error(SDC_ERR_NO_DEVICE, "no HIP device");
+    if (device < 0 || device >= dev_count) return sdc::set_error(SDC_ERR_INVALID_ARG, "device out of range");
+    if (hipSetDevice(device) != hipSuccess) return sdc::set_error(SDC_ERR_HIP, "hipSetDevice");
+    std::vector<void*> owned;
+    auto release = [&]() {
+        for (void* p : owned) (void)hipFree(p);
+    };
+    auto alloc = [&](void** p, size_t bytes) {
+        if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        owned.push_back(*p);
+        return true;
+    };
+    int32_t* d_nbr = nullptr;
+    int32_t* d_order = nullptr;
+    float* d_j = nullptr;
+    float* d_dv = nullptr;
+    double* d_S = nullptr;
+    double* d_cone = nullptr;
+    double* d_partial = nullptr;
+    double* d_info = nullptr;
+    unsigned long long* d_acc = nullptr;
+    long long* d_hist = nullptr;
+    const int n_part = sdc::mc_energy_blocks(n_sites);
+    bool ok = alloc((void**)&d_nbr, b.nbr.size() * 4) && alloc((void**)&d_j, b.jv.size() * 4) &&
+              (b.dv.empty() || alloc((void**)&d_dv, b.dv.size() * 4)) &&
+              alloc((void**)&d_order, (size_t)n_sites * 4) && alloc((void**)&d_S, (size_t)n_sites * 24) &&
+              alloc((void**)&d_cone, 16) && alloc((void**)&d_acc, 8) && alloc((void**)&d_partial, (size_t)n_part * 8) &&
+              alloc((void**)&d_info, 24) && (!accepted_host || alloc((void**)&d_hist, (size_t)n_sweeps * 8));
+    if (!ok) {
+        release();
+        return sdc::set_error(SDC_ERR_OOM, "hipMalloc failed");
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_nbr, b.nbr.data(), b.nbr.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_j, b.jv.data(), b.jv.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && d_dv) e = hipMemcpyAsync(d_dv, b.dv.data(), b.dv.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_order, order.data(), (size_t)n_sites * 4, hipMemcpyHostToDevice, hs);
+    sdc::McArgs ma{};
+    ma.n = n_sites;
+    ma.z_max = b.z;
+    ma.nbr = d_nbr;
+    ma.jval = d_j;
+    ma.dvec = d_dv;
+    ma.A = spec->A;
+    ma.Hz = spec->Hz;
+    ma.seed = spec->seed;
+    ma.acc_target = spec->acc_target;
+    ma.S = d_S;
+    ma.cone = d_cone;
+    ma.accepted = d_acc;
+    std::vector<const int32_t*> class_sites((size_t)n_col);
+    for (int c = 0; c < n_col; ++c) class_sites[(size_t)c] = d_order + start[(size_t)c];
+    int le = e == hipSuccess ? sdc::launch_mc_setup(ma, init_dev, spec->cone0, stream) : (int)e;
+    int64_t sweep = 0;
+    double T_last = spec->T_start;
+    mc_schedule(spec, [&](double T) {
+        if (le == 0)
+            le = sdc::launch_mc_sweep(ma, class_sites.data(), count.data(), n_col, T, sweep, d_hist, stream);
+        ++sweep;
+        T_last = T;
+    });
+    if (le == 0) le = sdc::launch_mc_finish(ma, d_partial, T_last, state_dev, d_info, stream);
+    double info[3] = {0.0, 0.0, 0.0};
+    if (le == 0) le = (int)hipMemcpyAsync(info, d_info, 24, hipMemcpyDeviceToHost, hs);
+    if (le == 0 && accepted_host && n_sweeps > 0)
+        le = (int)hipMemcpyAsync(accepted_host, d_hist, (size_t)n_sweeps * 8, hipMemcpyDeviceToHost, hs);
+    const hipError_t se = hipStreamSynchronize(hs);
+    release();
+    if (le != 0) return sdc::set_error(SDC_ERR_HIP, hipGetErrorString((hipError_t)le));
+    if (se != hipSuccess) return sdc::set_error(SDC_ERR_HIP, hipGetErrorString(se));
+    if (info_host) {
+        info_host[0] = info[0];
+        info_host[1] = info[1];
+        info_host[2] = info[2];
+        info_host[3] = (double)n_col;
+    }
+    return sdc::set_error(SDC_OK, "");
 }

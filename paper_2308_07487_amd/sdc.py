@@ -43,6 +43,15 @@ class CorrSpec(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class McSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("cells", ctypes.c_int32 * 3), ("coupling", ctypes.c_int32),
+                ("r_cut", ctypes.c_float), ("J", ctypes.c_double), ("D", ctypes.c_double),
+                ("A", ctypes.c_double), ("Hz", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("T_start", ctypes.c_double), ("T_end", ctypes.c_double), ("cool", ctypes.c_double),
+                ("sweeps_per_T", ctypes.c_int64), ("sweeps_final", ctypes.c_int64),
+                ("cone0", ctypes.c_double), ("acc_target", ctypes.c_double)]
+
+
 class SqSpec(ctypes.Structure):
     _fields_ = [("n_origins", ctypes.c_int32), ("n_lags", ctypes.c_int32),
                 ("origin_stride", ctypes.c_int32), ("flags", ctypes.c_int32)]
@@ -62,7 +71,8 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_status_string", "sdc_last_error", "sdc_layout_keys", "sdc_traj_generate",
            "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_timings", "sdc_batch_info",
            "sdc_batch_destroy", "sdc_plan_structure_factor", "sdc_sq_create", "sdc_sq_accumulate",
-           "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy")
+           "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy", "sdc_mc_n_sweeps",
+           "sdc_mc_anneal")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -102,6 +112,8 @@ def lib():
         L.sdc_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.sdc_batch_destroy.argtypes = [P]
         L.sdc_plan_structure_factor.argtypes = [P, P, i32, P, P, P]
+        L.sdc_mc_n_sweeps.argtypes = [ctypes.POINTER(McSpec), ctypes.POINTER(i64)]
+        L.sdc_mc_anneal.argtypes = [P, i64, ctypes.POINTER(McSpec), P, P, P, P, ctypes.c_int, P]
         L.sdc_sq_create.argtypes = [P, i64, P, i32, ctypes.POINTER(SqSpec), ctypes.c_int, ctypes.POINTER(P)]
         L.sdc_sq_accumulate.argtypes = [P, P, i64, P]
         L.sdc_sq_finalize.argtypes = [P, P, P, P]
@@ -371,6 +383,47 @@ def traj_generate(positions, kind, frames_out, cells=(0, 0, 0), J=1.0, dt=0.01, 
     _check(lib().sdc_traj_generate(_np_ptr(pos), pos.shape[0], ctypes.byref(sp),
                                    _dev_ptr(frames_out, "torch.float32"), frames_out.shape[0],
                                    int(device), _stream_ptr(stream)), "sdc_traj_generate")
+
+
+def mc_spec(kind, cells=(0, 0, 0), coupling=COUPLING_NN_UNIFORM, r_cut=0.0, J=1.0, D=0.0, A=0.0, Hz=0.0,
+            seed=0, T_start=1.0, T_end=1.0, cool=0.9, sweeps_per_T=1, sweeps_final=0, cone0=np.pi,
+            acc_target=0.2):
+    m = McSpec()
+    m.kind = int(kind)
+    for a in range(3):
+        m.cells[a] = int(cells[a])
+    m.coupling, m.r_cut = int(coupling), float(r_cut)
+    m.J, m.D, m.A, m.Hz = float(J), float(D), float(A), float(Hz)
+    m.seed = int(seed)
+    m.T_start, m.T_end, m.cool = float(T_start), float(T_end), float(cool)
+    m.sweeps_per_T, m.sweeps_final = int(sweeps_per_T), int(sweeps_final)
+    m.cone0, m.acc_target = float(cone0), float(acc_target)
+    return m
+
+
+def mc_n_sweeps(spec):
+    n = ctypes.c_int64()
+    _check(lib().sdc_mc_n_sweeps(ctypes.byref(spec), ctypes.byref(n)), "sdc_mc_n_sweeps")
+    return int(n.value)
+
+
+def mc_anneal(positions, spec, init_state, state_out, device=0, stream=None, history=True):
+    """Annealed Metropolis sweeps (Sec. 2.1, Sec. 4.3) from init_state into
+    state_out (float32 device tensors [N][3]).  Returns (accepted moves per
+    sweep or None, energy per site, final cone, last T, colour classes)."""
+    pos = np.ascontiguousarray(positions, dtype=np.float32)
+    n = pos.shape[0]
+    for t in (init_state, state_out):
+        if tuple(t.shape) != (n, 3):
+            raise ValueError("states must have shape [n_sites][3]")
+    acc = np.zeros(max(mc_n_sweeps(spec), 1), dtype=np.int64) if history else None
+    info = np.zeros(4)
+    _check(lib().sdc_mc_anneal(_np_ptr(pos), n, ctypes.byref(spec), _dev_ptr(init_state, "torch.float32"),
+                               _dev_ptr(state_out, "torch.float32"), _np_ptr(acc) if history else None,
+                               _np_ptr(info), int(device), _stream_ptr(stream)), "sdc_mc_anneal")
+    if history:
+        acc = acc[:mc_n_sweeps(spec)]
+    return acc, float(info[0]), float(info[1]), float(info[2]), int(info[3])
 
 
 class StructureFactor:

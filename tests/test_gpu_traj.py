@@ -219,3 +219,89 @@ def test_rk4_cone_wave_full_model_exact(torch_dev, S):
     err = np.abs(fr.cpu().numpy() - exact).max()
     print(f"  max error {err:.2e}", flush=True)
     assert err < 3e-5
+
+
+# --------------------------------------------------------------------------
+# thermalised starts: Metropolis Monte Carlo with simulated annealing
+# --------------------------------------------------------------------------
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("kind", ["sc", "bcc", "radial"])
+def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind):
+    """Annealed Metropolis sweeps with every term of Eq. (1): the GPU's colour
+    classes, Philox moves and cone adaptation against the oracle's on the
+    same bonds (fp32 tables, as the library builds them).  Accepted moves per
+    sweep agree exactly; the states agree to the fp32 output."""
+    _say(f"mc anneal {kind}")
+    D, A, Hz, seed = 0.3, 0.2, 0.4, 0x5DC0A101
+    if kind == "radial":
+        pos = inputs.ball_positions(300, 3.0, seed=9)
+        row, col, Jv = _cutoff_csr(pos, 1.0, 1.5)
+        rij = pos[col].astype(np.float64) - pos[np.repeat(np.arange(pos.shape[0]), np.diff(row))].astype(np.float64)
+        Dv = D * rij / np.linalg.norm(rij, axis=1, keepdims=True)
+        spec = S.mc_spec(S.BINS_RADIAL, coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5, J=1.0)
+    else:
+        L = (4, 6, 5) if kind == "sc" else (3, 4, 4)
+        pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+        sign = 0x5DC0A102 if kind == "bcc" else None
+        row, col, Jv = _nn_csr(pos, L, kind, -1.0, sign_seed=sign, orc=orc)
+        Dv = _dmi_lattice(pos.shape[0], kind, D)
+        spec = S.mc_spec(S.BINS_SC if kind == "sc" else S.BINS_BCC, cells=L,
+                         coupling=S.COUPLING_NN_RANDOM_SIGN if sign else S.COUPLING_NN_UNIFORM, J=-1.0)
+    spec.D, spec.A, spec.Hz = D, A, Hz
+    spec.seed = sign if (kind == "bcc") else seed
+    spec.T_start, spec.T_end, spec.cool, spec.sweeps_per_T, spec.sweeps_final = 2.0, 0.3, 0.7, 3, 6
+    spec.cone0, spec.acc_target = np.pi, 0.2
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=23)[0]
+    st = torch_dev.from_numpy(init).cuda()
+    out = torch_dev.zeros_like(st)
+    acc, E, cone, T, ncol = S.mc_anneal(pos, spec, st, out)
+    ref = orc.mc_anneal(row, col, _f32(Jv), init, spec.seed, 2.0, 0.3, 0.7, 3, 6, cone0=np.pi, acc_target=0.2,
+                        D=_f32(Dv), A=A, Hz=Hz)
+    got = out.cpu().numpy()
+    print(f"  sweeps {acc.shape[0]}, colours {ncol}/{ref[5]}, accepted {acc.sum()}/{ref[1].sum()}, "
+          f"state diff {np.abs(got - ref[0]).max():.2e}, E {E:.9f} / {ref[2]:.9f}", flush=True)
+    assert ncol == ref[5] and T == ref[4]
+    np.testing.assert_array_equal(acc, ref[1])
+    assert np.abs(got - ref[0]).max() < 2e-7
+    assert abs(E - ref[2]) < 1e-10 * max(1.0, abs(ref[2])) and abs(cone - ref[3]) < 1e-12
+    assert 0 < acc.sum() < acc.shape[0] * n  # some moves accepted, some rejected
+
+
+def test_mc_independent_spins_equilibrium(torch_dev, S):
+    """20000 spins without bonds in a field and anisotropy sample
+    p(S_z) ~ exp((A S_z^2 + H_z S_z) / T): mean and second moment of S_z
+    within 4 standard errors of the quadrature."""
+    from scipy.integrate import quad
+    _say("mc independent spins")
+    n, T, A, Hz = 20000, 0.5, 0.3, 0.4
+    pos = inputs.ball_positions(n, 1.0e4, seed=10)  # far apart: no pair within r_cut
+    spec = S.mc_spec(S.BINS_RADIAL, coupling=S.COUPLING_EXP_CUTOFF, r_cut=0.5, J=1.0, A=A, Hz=Hz,
+                     seed=0x5DC0A103, T_start=T, T_end=T, sweeps_per_T=1, sweeps_final=300)
+    st = torch_dev.from_numpy(inputs.random_unit_frames(1, n, seed=24)[0]).cuda()
+    acc, E, cone, Tl, ncol = S.mc_anneal(pos, spec, st, st)
+    assert ncol == 1
+    s = st.cpu().numpy().astype(np.float64)
+    w = lambda x: np.exp((A * x * x + Hz * x) / T)
+    Z = quad(w, -1, 1)[0]
+    m1 = quad(lambda x: x * w(x), -1, 1)[0] / Z
+    m2 = quad(lambda x: x * x * w(x), -1, 1)[0] / Z
+    se = np.sqrt((m2 - m1 * m1) / n)
+    print(f"  <Sz> {s[:, 2].mean():.5f} vs {m1:.5f} (se {se:.1e}), final cone {cone:.3f}", flush=True)
+    assert abs(s[:, 2].mean() - m1) < 4 * se
+    assert abs((s[:, 2] ** 2).mean() - m2) < 4 * np.sqrt(1.0 / n)
+
+
+def test_mc_rejects_bad_specs(torch_dev, S):
+    pos = inputs.sc_positions((4, 4, 4))
+    st = torch_dev.zeros((64, 3), device="cuda")
+    for field, value in [("cool", 1.0), ("T_end", 0.0), ("cone0", 4.0), ("acc_target", 0.7),
+                         ("sweeps_per_T", 0)]:
+        spec = S.mc_spec(S.BINS_SC, cells=(4, 4, 4), T_start=1.0, T_end=0.5, sweeps_final=2)
+        setattr(spec, field, value)
+        with pytest.raises(S.SdcError):
+            S.mc_anneal(pos, spec, st, st)

@@ -495,6 +495,34 @@ sdc_status sdc_mc_anneal(const float* positions_host, int64_t n_sites, const sdc
                          const float* init_dev, float* state_dev, int64_t* accepted_host,
                          double* info_host, int device, void* stream);
 
+typedef struct sdc_mc sdc_mc;
+
+/* The same as a reusable object: sdc_mc_create builds the bonds, the colour
+ * classes and the device state once (synchronously) for the model fields of
+ * spec (kind .. Hz; seed only for random bond signs).  Errors: INVALID_ARG,
+ * UNSUPPORTED, OOM, HIP, NO_DEVICE. */
+sdc_status sdc_mc_create(const float* positions_host, int64_t n_sites, const sdc_mc_spec* spec,
+                         int device, sdc_mc** out);
+
+/* Run the schedule of `schedule` (seed, T_start .. acc_target; its model
+ * fields are ignored) from init_dev ([n_sites][3] fp32 device), or, when
+ * init_dev is NULL, from the FP64 state the previous run left; the final
+ * state goes to state_dev as fp32.  Sweep indices (the Philox counter) start
+ * at 0 in every run: use a new seed for an independent run.  Queued on the
+ * stream without host synchronisation unless accepted_host or info_host
+ * (as in sdc_mc_anneal) is requested.  Errors: INVALID_ARG, STATE (NULL
+ * init_dev before any run), OOM, HIP. */
+sdc_status sdc_mc_run(sdc_mc* mc, const sdc_mc_spec* schedule, const float* init_dev, float* state_dev,
+                      int64_t* accepted_host, double* info_host, void* stream);
+
+/* Duration (milliseconds) of the sweeps of the most recent run (HIP events
+ * on its stream around the sweep kernels).  Waits for them.  Errors:
+ * INVALID_ARG, STATE, HIP. */
+sdc_status sdc_mc_timings(sdc_mc* mc, double* ms);
+
+/* Free the object (waits for the device).  NULL is a no-op. */
+sdc_status sdc_mc_destroy(sdc_mc* mc);
+
 #ifdef __cplusplus
 }
 #endif

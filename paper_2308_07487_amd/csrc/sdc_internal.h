@@ -342,22 +342,26 @@ int launch_traj(const TrajArgs& a, void* stream);
 struct McArgs {
     int64_t n;
     int z_max;
-    const int32_t* nbr;        // [n][z_max], -1 = none
-    const float* jval;         // [n][z_max]
-    const float* dvec;         // [n][z_max][3] DMI vectors, or null
+    const int32_t* site_of;    // [n] site of each slot (slots colour-major)
+    const int32_t* nbr;        // [n slots][z_max] neighbour slots, -1 = none
+    const float* jval;         // [n slots][z_max]
+    const float* dvec;         // [n slots][z_max][3] DMI vectors, or null
     double A, Hz;              // anisotropy and field of Eq. (1)
     uint64_t seed;             // Philox key of the moves
     double acc_target;         // acceptance-rate target of the cone adaptation
-    double* S;                 // [n][3] FP64 state
+    double* S;                 // [n slots][3] FP64 state
     double* cone;              // [2]: cone half-angle, its cosine
-    unsigned long long* accepted;  // accepted moves of the current sweep
+    unsigned long long* accepted;  // accepted moves of the current sweep (mc_counter_bytes())
 };
 int mc_energy_blocks(int64_t n);
+size_t mc_counter_bytes();
+// Loads init (fp32, or keeps the FP64 state when init is null), sets the cone.
 int launch_mc_setup(const McArgs& a, const float* init, double cone0, void* stream);
-// One sweep: every colour class in order, then the cone update (history[sweep]
-// receives the accepted moves when history is not null).
-int launch_mc_sweep(const McArgs& a, const int32_t* const* class_sites, const int64_t* class_count, int n_classes,
-                    double T, int64_t sweep, long long* history, void* stream);
+// One sweep: every colour class in order (class c = slots class_start[c] ..
+// class_start[c + 1]), then the cone update (history[sweep] receives the
+// accepted moves when history is not null).
+int launch_mc_sweep(const McArgs& a, const int64_t* class_start, int n_classes, double T, int64_t sweep,
+                    long long* history, void* stream);
 // Energy per site, final cone and temperature into info[0..2]; state as fp32.
 int launch_mc_finish(const McArgs& a, double* partial, double T_last, float* out, double* info, void* stream);
 

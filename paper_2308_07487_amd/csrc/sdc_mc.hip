@@ -3,7 +3,10 @@
 //
 // Sites are split into colour classes that share no bond (greedy colouring
 // on the host), so one class is updated in parallel, one thread per site.
-// The state is FP64.  Every random number is a Philox4x32-10 draw of the
+// The state is FP64 and stored colour-major: slot k holds site site_of[k],
+// the slots of one class are contiguous and the bond tables are in slot
+// order with neighbours given as slots, so a class's own states, bond
+// tables and its neighbours' states are read as contiguous runs.  Every random number is a Philox4x32-10 draw of the
 // (site, sweep) counter, so a sweep's result does not depend on the order in
 // which threads run; the cone and the acceptance counter live in device
 // memory and are updated by a one-thread kernel after each sweep, so a whole
@@ -17,36 +20,42 @@ namespace sdc {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+// The accepted moves of a sweep are counted in kMcCounters counters, one per
+// 128-byte line (workgroup b adds to counter b mod kMcCounters), so that the
+// workgroups' atomics do not all queue on one address.
+constexpr int kMcCounters = 64;
+constexpr int kMcCounterStride = 16;  // u64 words between counters
 
 // One colour class of one sweep.  Site i's move: trial spin in a cone of
 // half-angle `cone` about S_i (cos a uniform in [cos cone, 1], azimuth
 // uniform), Metropolis acceptance at temperature T.  Counter = (i low,
 // sweep low, i high, 2^31 | sweep high), key = seed: u_k = (w_k + 1/2) 2^-32.
-__global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, const int32_t* __restrict__ sites, int64_t count,
-                                                        double T, int64_t sweep) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, int64_t k0, int64_t count, double T,
+                                                        int64_t sweep) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool accepted = false;
-    if (k < count) {
-        const int64_t i = sites[k];
+    if (t < count) {
+        const int64_t k = k0 + t;           // slot
+        const int64_t i = a.site_of[k];     // site index: the Philox counter
         // field of the neighbours: sum_j (J_ij S_j + D_ij x S_j)
         double w0 = 0.0, w1 = 0.0, w2 = 0.0;
         for (int e = 0; e < a.z_max; ++e) {
-            const int32_t j = a.nbr[i * a.z_max + e];
+            const int32_t j = a.nbr[k * a.z_max + e];
             if (j < 0) continue;
-            const double J = a.jval[i * a.z_max + e];
+            const double J = a.jval[k * a.z_max + e];
             const double y0 = a.S[3 * (int64_t)j], y1 = a.S[3 * (int64_t)j + 1], y2 = a.S[3 * (int64_t)j + 2];
             w0 += J * y0;
             w1 += J * y1;
             w2 += J * y2;
             if (a.dvec) {
-                const float* d = a.dvec + 3 * (i * a.z_max + e);
+                const float* d = a.dvec + 3 * (k * a.z_max + e);
                 const double d0 = d[0], d1 = d[1], d2 = d[2];
                 w0 += d1 * y2 - d2 * y1;
                 w1 += d2 * y0 - d0 * y2;
                 w2 += d0 * y1 - d1 * y0;
             }
         }
-        double* si = a.S + 3 * i;
+        double* si = a.S + 3 * k;
         const double s0 = si[0], s1 = si[1], s2 = si[2];
         uint32_t c[4] = {(uint32_t)i, (uint32_t)sweep, (uint32_t)((uint64_t)i >> 32),
                          0x80000000u | (uint32_t)((uint64_t)sweep >> 32)};
@@ -84,15 +93,27 @@ __global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, const int32_t*
             accepted = true;
         }
     }
+    __shared__ unsigned int wave_acc[4];
     const unsigned long long ball = __ballot(accepted);
-    if ((threadIdx.x & 63) == 0 && ball != 0ull)
-        atomicAdd(a.accepted, (unsigned long long)__popcll(ball));
+    if ((threadIdx.x & 63) == 0) wave_acc[threadIdx.x >> 6] = (unsigned int)__popcll(ball);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long sum = (unsigned long long)wave_acc[0] + wave_acc[1] + wave_acc[2] + wave_acc[3];
+        if (sum) atomicAdd(a.accepted + (blockIdx.x % kMcCounters) * kMcCounterStride, sum);
+    }
 }
 
-// After a sweep: record the accepted moves, adapt the cone, clear the counter.
-__global__ void mc_cone_kernel(McArgs a, long long* history, int64_t sweep) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long acc = *a.accepted;
+// After a sweep (one wave): gather the counters, clear them, record the
+// accepted moves, adapt the cone.
+__global__ __launch_bounds__(64) void mc_cone_kernel(McArgs a, long long* history, int64_t sweep) {
+    __shared__ unsigned long long part[kMcCounters];
+    const int t = threadIdx.x;
+    part[t] = a.accepted[t * kMcCounterStride];
+    a.accepted[t * kMcCounterStride] = 0ull;
+    __syncthreads();
+    if (t != 0) return;
+    unsigned long long acc = 0ull;
+    for (int c = 0; c < kMcCounters; ++c) acc += part[c];
     if (history) history[sweep] = (long long)acc;
     const double rate = (double)acc / (double)a.n;
     double c = a.cone[0];
@@ -102,19 +123,18 @@ __global__ void mc_cone_kernel(McArgs a, long long* history, int64_t sweep) {
         c = fmin(kPi, 1.1 * c);
     a.cone[0] = c;
     a.cone[1] = cos(c);
-    *a.accepted = 0ull;
 }
 
-__global__ void mc_setup_kernel(McArgs a, double cone0) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void mc_setup_kernel(McArgs a, double cone0) {
+    a.accepted[threadIdx.x * kMcCounterStride] = 0ull;
+    if (threadIdx.x != 0) return;
     a.cone[0] = cone0;
     a.cone[1] = cos(cone0);
-    *a.accepted = 0ull;
 }
 
 __global__ __launch_bounds__(256) void mc_load_kernel(McArgs a, const float* __restrict__ init) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * a.n; x += (int64_t)gridDim.x * blockDim.x)
-        a.S[x] = (double)init[x];
+        a.S[x] = (double)init[3 * (int64_t)a.site_of[x / 3] + x % 3];
 }
 
 // Energy of Eq. (1) per block: half of each site's bond energies (each bond
@@ -122,16 +142,16 @@ __global__ __launch_bounds__(256) void mc_load_kernel(McArgs a, const float* __r
 __global__ __launch_bounds__(256) void mc_energy_kernel(McArgs a, double* __restrict__ partial) {
     __shared__ double red[256];
     double e = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double* si = a.S + 3 * i;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += (int64_t)gridDim.x * blockDim.x) {
+        const double* si = a.S + 3 * k;
         double eb = 0.0;
-        for (int k = 0; k < a.z_max; ++k) {
-            const int32_t j = a.nbr[i * a.z_max + k];
+        for (int e = 0; e < a.z_max; ++e) {
+            const int32_t j = a.nbr[k * a.z_max + e];
             if (j < 0) continue;
             const double* sj = a.S + 3 * (int64_t)j;
-            eb += (double)a.jval[i * a.z_max + k] * (si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2]);
+            eb += (double)a.jval[k * a.z_max + e] * (si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2]);
             if (a.dvec) {
-                const float* d = a.dvec + 3 * (i * a.z_max + k);
+                const float* d = a.dvec + 3 * (k * a.z_max + e);
                 const double cx = si[1] * sj[2] - si[2] * sj[1];
                 const double cy = si[2] * sj[0] - si[0] * sj[2];
                 const double cz = si[0] * sj[1] - si[1] * sj[0];
@@ -153,7 +173,7 @@ __global__ __launch_bounds__(256) void mc_energy_kernel(McArgs a, double* __rest
 // in block order), cone, last temperature.
 __global__ __launch_bounds__(256) void mc_out_kernel(McArgs a, float* __restrict__ out) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * a.n; x += (int64_t)gridDim.x * blockDim.x)
-        out[x] = (float)a.S[x];
+        out[3 * (int64_t)a.site_of[x / 3] + x % 3] = (float)a.S[x];
 }
 
 __global__ void mc_info_kernel(McArgs a, const double* __restrict__ partial, int n_partial, double T_last,
@@ -175,20 +195,23 @@ unsigned grid_of(int64_t n) {
 
 int mc_energy_blocks(int64_t n) { return (int)grid_of(n); }
 
+size_t mc_counter_bytes() { return (size_t)kMcCounters * kMcCounterStride * sizeof(unsigned long long); }
+
 int launch_mc_setup(const McArgs& a, const float* init, double cone0, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(mc_load_kernel, dim3(grid_of(3 * a.n)), dim3(256), 0, s, a, init);
+    if (init) hipLaunchKernelGGL(mc_load_kernel, dim3(grid_of(3 * a.n)), dim3(256), 0, s, a, init);
     hipLaunchKernelGGL(mc_setup_kernel, dim3(1), dim3(64), 0, s, a, cone0);
     return (int)hipGetLastError();
 }
 
-int launch_mc_sweep(const McArgs& a, const int32_t* const* class_sites, const int64_t* class_count, int n_classes,
-                    double T, int64_t sweep, long long* history, void* stream) {
+int launch_mc_sweep(const McArgs& a, const int64_t* class_start, int n_classes, double T, int64_t sweep,
+                    long long* history, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     for (int c = 0; c < n_classes; ++c) {
-        if (class_count[c] == 0) continue;
-        const unsigned grid = (unsigned)((class_count[c] + 255) / 256);
-        hipLaunchKernelGGL(mc_colour_kernel, dim3(grid), dim3(256), 0, s, a, class_sites[c], class_count[c], T, sweep);
+        const int64_t count = class_start[c + 1] - class_start[c];
+        if (count == 0) continue;
+        const unsigned grid = (unsigned)((count + 255) / 256);
+        hipLaunchKernelGGL(mc_colour_kernel, dim3(grid), dim3(256), 0, s, a, class_start[c], count, T, sweep);
     }
     hipLaunchKernelGGL(mc_cone_kernel, dim3(1), dim3(64), 0, s, a, history, sweep);
     return (int)hipGetLastError();

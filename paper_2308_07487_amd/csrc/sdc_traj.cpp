@@ -322,10 +322,48 @@ extern "C" sdc_status sdc_mc_n_sweeps(const sdc_mc_spec* spec, int64_t* n_sweeps
     return sdc::set_error(SDC_OK, "");
 }
 
-extern "C" sdc_status sdc_mc_anneal(const float* positions_host, int64_t n_sites, const sdc_mc_spec* spec,
-                                    const float* init_dev, float* state_dev, int64_t* accepted_host,
-                                    double* info_host, int device, void* stream) {
-    if (!positions_host || !spec || !init_dev || !state_dev) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+struct sdc_mc {
+    int device = 0;
+    sdc_mc_spec spec{};
+    int64_t n = 0;
+    int n_col = 0;
+    std::vector<int64_t> start;          // first slot of each colour class, and n
+    std::vector<void*> owned;
+    sdc::McArgs args{};
+    double* d_partial = nullptr;
+    double* d_info = nullptr;
+    long long* d_hist = nullptr;
+    int64_t hist_cap = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool timed = false;
+    bool loaded = false;                 // the FP64 state holds a configuration
+
+    ~sdc_mc() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+bool mc_alloc(sdc_mc* m, void** p, size_t bytes) {
+    if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    m->owned.push_back(*p);
+    return true;
+}
+
+}  // namespace
+
+extern "C" sdc_status sdc_mc_create(const float* positions_host, int64_t n_sites, const sdc_mc_spec* spec, int device,
+                                    sdc_mc** out) {
+    if (!out) return sdc::set_error(SDC_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (!positions_host || !spec) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
     if (n_sites < 1 || n_sites > ((int64_t)1 << 26)) return sdc::set_error(SDC_ERR_INVALID_ARG, "n_sites out of range");
     sdc_status s = mc_check(spec);
     if (s != SDC_OK) return s;
@@ -341,112 +379,192 @@ extern "C" sdc_status sdc_mc_anneal(const float* positions_host, int64_t n_sites
     std::string err;
     s = build_bonds(positions_host, n_sites, &ts, &b, &err);
     if (s != SDC_OK) return sdc::set_error(s, err);
-    // greedy colouring in site order, then the sites grouped by colour
-    std::vector<int32_t> colour((size_t)n_sites, -1);
-    int n_col = 0;
-    std::vector<char> used;
-    for (int64_t i = 0; i < n_sites; ++i) {
-        used.assign((size_t)n_col + 1, 0);
-        for (int e = 0; e < b.z; ++e) {
-            const int32_t j = b.nbr[i * b.z + e];
-            if (j >= 0 && j < i) used[(size_t)colour[j]] = 1;
-        }
-        int c = 0;
-        while (used[(size_t)c]) ++c;
-        colour[i] = c;
-        n_col = std::max(n_col, c + 1);
-    }
-    std::vector<int64_t> count((size_t)n_col, 0), start((size_t)n_col + 1, 0);
-    for (int64_t i = 0; i < n_sites; ++i) ++count[(size_t)colour[i]];
-    for (int c = 0; c < n_col; ++c) start[(size_t)c + 1] = start[(size_t)c] + count[(size_t)c];
-    std::vector<int32_t> order((size_t)n_sites);
-    {
-        std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t i = 0; i < n_sites; ++i) order[(size_t)fill[(size_t)colour[i]]++] = (int32_t)i;
-    }
-    const int64_t n_sweeps = mc_schedule(spec, [](double) {});
-
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0)
         return sdc::set_error(SDC_ERR_NO_DEVICE, "no HIP device");
     if (device < 0 || device >= dev_count) return sdc::set_error(SDC_ERR_INVALID_ARG, "device out of range");
     if (hipSetDevice(device) != hipSuccess) return sdc::set_error(SDC_ERR_HIP, "hipSetDevice");
-    std::vector<void*> owned;
-    auto release = [&]() {
-        for (void* p : owned) (void)hipFree(p);
-    };
-    auto alloc = [&](void** p, size_t bytes) {
-        if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
+    sdc_mc* m = nullptr;
+    try {
+        m = new sdc_mc();
+        m->device = device;
+        m->spec = *spec;
+        m->n = n_sites;
+        // greedy colouring in site order, then the sites grouped by colour
+        std::vector<int32_t> colour((size_t)n_sites, -1);
+        std::vector<char> used;
+        for (int64_t i = 0; i < n_sites; ++i) {
+            used.assign((size_t)m->n_col + 1, 0);
+            for (int e = 0; e < b.z; ++e) {
+                const int32_t j = b.nbr[i * b.z + e];
+                if (j >= 0 && j < i) used[(size_t)colour[j]] = 1;
+            }
+            int c = 0;
+            while (used[(size_t)c]) ++c;
+            colour[i] = c;
+            m->n_col = std::max(m->n_col, c + 1);
         }
-        owned.push_back(*p);
-        return true;
-    };
-    int32_t* d_nbr = nullptr;
-    int32_t* d_order = nullptr;
-    float* d_j = nullptr;
-    float* d_dv = nullptr;
-    double* d_S = nullptr;
-    double* d_cone = nullptr;
-    double* d_partial = nullptr;
-    double* d_info = nullptr;
-    unsigned long long* d_acc = nullptr;
-    long long* d_hist = nullptr;
-    const int n_part = sdc::mc_energy_blocks(n_sites);
-    bool ok = alloc((void**)&d_nbr, b.nbr.size() * 4) && alloc((void**)&d_j, b.jv.size() * 4) &&
-              (b.dv.empty() || alloc((void**)&d_dv, b.dv.size() * 4)) &&
-              alloc((void**)&d_order, (size_t)n_sites * 4) && alloc((void**)&d_S, (size_t)n_sites * 24) &&
-              alloc((void**)&d_cone, 16) && alloc((void**)&d_acc, 8) && alloc((void**)&d_partial, (size_t)n_part * 8) &&
-              alloc((void**)&d_info, 24) && (!accepted_host || alloc((void**)&d_hist, (size_t)n_sweeps * 8));
-    if (!ok) {
-        release();
-        return sdc::set_error(SDC_ERR_OOM, "hipMalloc failed");
+        // colour-major slots: class c takes slots start[c] .. start[c + 1], sites
+        // in index order; bond tables rewritten in slot order with slot
+        // neighbours
+        std::vector<int64_t>& start = m->start;
+        start.assign((size_t)m->n_col + 1, 0);
+        for (int64_t i = 0; i < n_sites; ++i) ++start[(size_t)colour[i] + 1];
+        for (int c = 0; c < m->n_col; ++c) start[(size_t)c + 1] += start[(size_t)c];
+        std::vector<int32_t> order((size_t)n_sites), slot((size_t)n_sites);
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n_sites; ++i) {
+            const int64_t k = fill[(size_t)colour[i]]++;
+            order[(size_t)k] = (int32_t)i;
+            slot[(size_t)i] = (int32_t)k;
+        }
+        {
+            std::vector<int32_t> nbr(b.nbr.size());
+            std::vector<float> jv(b.jv.size()), dv(b.dv.size());
+            for (int64_t k = 0; k < n_sites; ++k) {
+                const int64_t i = order[(size_t)k];
+                for (int e = 0; e < b.z; ++e) {
+                    const int32_t j = b.nbr[i * b.z + e];
+                    nbr[k * b.z + e] = j < 0 ? -1 : slot[(size_t)j];
+                    jv[k * b.z + e] = b.jv[i * b.z + e];
+                    if (!dv.empty())
+                        for (int c = 0; c < 3; ++c) dv[(k * b.z + e) * 3 + c] = b.dv[(i * b.z + e) * 3 + c];
+                }
+            }
+            b.nbr.swap(nbr);
+            b.jv.swap(jv);
+            b.dv.swap(dv);
+        }
+
+        int32_t* d_nbr = nullptr;
+        int32_t* d_order = nullptr;
+        float* d_j = nullptr;
+        float* d_dv = nullptr;
+        double* d_S = nullptr;
+        double* d_cone = nullptr;
+        unsigned long long* d_acc = nullptr;
+        const int n_part = sdc::mc_energy_blocks(n_sites);
+        const bool ok = mc_alloc(m, (void**)&d_nbr, b.nbr.size() * 4) && mc_alloc(m, (void**)&d_j, b.jv.size() * 4) &&
+                        (b.dv.empty() || mc_alloc(m, (void**)&d_dv, b.dv.size() * 4)) &&
+                        mc_alloc(m, (void**)&d_order, (size_t)n_sites * 4) &&
+                        mc_alloc(m, (void**)&d_S, (size_t)n_sites * 24) && mc_alloc(m, (void**)&d_cone, 16) &&
+                        mc_alloc(m, (void**)&d_acc, sdc::mc_counter_bytes()) && mc_alloc(m, (void**)&m->d_partial, (size_t)n_part * 8) &&
+                        mc_alloc(m, (void**)&m->d_info, 24);
+        if (!ok) {
+            delete m;
+            return sdc::set_error(SDC_ERR_OOM, "hipMalloc failed");
+        }
+        hipError_t e = hipMemcpy(d_nbr, b.nbr.data(), b.nbr.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_j, b.jv.data(), b.jv.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && d_dv) e = hipMemcpy(d_dv, b.dv.data(), b.dv.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_order, order.data(), (size_t)n_sites * 4, hipMemcpyHostToDevice);
+        for (hipEvent_t& ev : m->ev)
+            if (e == hipSuccess) e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            delete m;
+            return sdc::set_error(SDC_ERR_HIP, hipGetErrorString(e));
+        }
+        sdc::McArgs& ma = m->args;
+        ma.n = n_sites;
+        ma.z_max = b.z;
+        ma.site_of = d_order;
+        ma.nbr = d_nbr;
+        ma.jval = d_j;
+        ma.dvec = d_dv;
+        ma.A = spec->A;
+        ma.Hz = spec->Hz;
+        ma.S = d_S;
+        ma.cone = d_cone;
+        ma.accepted = d_acc;
+    } catch (const std::bad_alloc&) {
+        delete m;
+        return sdc::set_error(SDC_ERR_OOM, "host allocation failed");
     }
+    *out = m;
+    return sdc::set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_run(sdc_mc* m, const sdc_mc_spec* schedule, const float* init_dev, float* state_dev,
+                                 int64_t* accepted_host, double* info_host, void* stream) {
+    if (!m || !schedule || !state_dev) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    if (!init_dev && !m->loaded) return sdc::set_error(SDC_ERR_STATE, "no configuration yet: pass init_dev");
+    sdc_status s = mc_check(schedule);
+    if (s != SDC_OK) return s;
+    const int64_t n_sweeps = mc_schedule(schedule, [](double) {});
+    if (hipSetDevice(m->device) != hipSuccess) return sdc::set_error(SDC_ERR_HIP, "hipSetDevice");
+    if (accepted_host && n_sweeps > m->hist_cap) {
+        void* p = nullptr;
+        if (!mc_alloc(m, &p, (size_t)n_sweeps * 8)) return sdc::set_error(SDC_ERR_OOM, "hipMalloc failed");
+        m->d_hist = (long long*)p;
+        m->hist_cap = n_sweeps;
+    }
+    sdc::McArgs ma = m->args;
+    ma.seed = schedule->seed;
+    ma.acc_target = schedule->acc_target;
     hipStream_t hs = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(d_nbr, b.nbr.data(), b.nbr.size() * 4, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_j, b.jv.data(), b.jv.size() * 4, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && d_dv) e = hipMemcpyAsync(d_dv, b.dv.data(), b.dv.size() * 4, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_order, order.data(), (size_t)n_sites * 4, hipMemcpyHostToDevice, hs);
-    sdc::McArgs ma{};
-    ma.n = n_sites;
-    ma.z_max = b.z;
-    ma.nbr = d_nbr;
-    ma.jval = d_j;
-    ma.dvec = d_dv;
-    ma.A = spec->A;
-    ma.Hz = spec->Hz;
-    ma.seed = spec->seed;
-    ma.acc_target = spec->acc_target;
-    ma.S = d_S;
-    ma.cone = d_cone;
-    ma.accepted = d_acc;
-    std::vector<const int32_t*> class_sites((size_t)n_col);
-    for (int c = 0; c < n_col; ++c) class_sites[(size_t)c] = d_order + start[(size_t)c];
-    int le = e == hipSuccess ? sdc::launch_mc_setup(ma, init_dev, spec->cone0, stream) : (int)e;
+    int le = sdc::launch_mc_setup(ma, init_dev, schedule->cone0, stream);
+    if (le == 0) le = (int)hipEventRecord(m->ev[0], hs);
     int64_t sweep = 0;
-    double T_last = spec->T_start;
-    mc_schedule(spec, [&](double T) {
+    double T_last = schedule->T_start;
+    long long* hist = accepted_host ? m->d_hist : nullptr;
+    mc_schedule(schedule, [&](double T) {
         if (le == 0)
-            le = sdc::launch_mc_sweep(ma, class_sites.data(), count.data(), n_col, T, sweep, d_hist, stream);
+            le = sdc::launch_mc_sweep(ma, m->start.data(), m->n_col, T, sweep, hist, stream);
         ++sweep;
         T_last = T;
     });
-    if (le == 0) le = sdc::launch_mc_finish(ma, d_partial, T_last, state_dev, d_info, stream);
+    if (le == 0) le = (int)hipEventRecord(m->ev[1], hs);
+    if (le == 0) le = sdc::launch_mc_finish(ma, m->d_partial, T_last, state_dev, m->d_info, stream);
+    if (le != 0) return sdc::set_error(SDC_ERR_HIP, hipGetErrorString((hipError_t)le));
+    m->loaded = true;
+    m->timed = true;
+    if (!accepted_host && !info_host) return sdc::set_error(SDC_OK, "");
     double info[3] = {0.0, 0.0, 0.0};
-    if (le == 0) le = (int)hipMemcpyAsync(info, d_info, 24, hipMemcpyDeviceToHost, hs);
+    le = (int)hipMemcpyAsync(info, m->d_info, 24, hipMemcpyDeviceToHost, hs);
     if (le == 0 && accepted_host && n_sweeps > 0)
-        le = (int)hipMemcpyAsync(accepted_host, d_hist, (size_t)n_sweeps * 8, hipMemcpyDeviceToHost, hs);
+        le = (int)hipMemcpyAsync(accepted_host, m->d_hist, (size_t)n_sweeps * 8, hipMemcpyDeviceToHost, hs);
     const hipError_t se = hipStreamSynchronize(hs);
-    release();
     if (le != 0) return sdc::set_error(SDC_ERR_HIP, hipGetErrorString((hipError_t)le));
     if (se != hipSuccess) return sdc::set_error(SDC_ERR_HIP, hipGetErrorString(se));
     if (info_host) {
         info_host[0] = info[0];
         info_host[1] = info[1];
         info_host[2] = info[2];
-        info_host[3] = (double)n_col;
+        info_host[3] = (double)m->n_col;
     }
     return sdc::set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_timings(sdc_mc* m, double* ms) {
+    if (!m || !ms) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    if (!m->timed) return sdc::set_error(SDC_ERR_STATE, "no run yet");
+    if (hipEventSynchronize(m->ev[1]) != hipSuccess) return sdc::set_error(SDC_ERR_HIP, "hipEventSynchronize");
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, m->ev[0], m->ev[1]) != hipSuccess)
+        return sdc::set_error(SDC_ERR_HIP, "hipEventElapsedTime");
+    *ms = t;
+    return sdc::set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_destroy(sdc_mc* m) {
+    if (!m) return SDC_OK;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    delete m;
+    return sdc::set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_anneal(const float* positions_host, int64_t n_sites, const sdc_mc_spec* spec,
+                                    const float* init_dev, float* state_dev, int64_t* accepted_host,
+                                    double* info_host, int device, void* stream) {
+    if (!init_dev || !state_dev) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    sdc_mc* m = nullptr;
+    sdc_status s = sdc_mc_create(positions_host, n_sites, spec, device, &m);
+    if (s != SDC_OK) return s;
+    s = sdc_mc_run(m, spec, init_dev, state_dev, accepted_host, info_host, stream);
+    if (s == SDC_OK && !accepted_host && !info_host && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        s = sdc::set_error(SDC_ERR_HIP, "hipStreamSynchronize");
+    const std::string keep = sdc_last_error();
+    (void)sdc_mc_destroy(m);
+    return s == SDC_OK ? s : sdc::set_error(s, keep);
 }

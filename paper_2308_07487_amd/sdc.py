@@ -72,7 +72,7 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_timings", "sdc_batch_info",
            "sdc_batch_destroy", "sdc_plan_structure_factor", "sdc_sq_create", "sdc_sq_accumulate",
            "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy", "sdc_mc_n_sweeps",
-           "sdc_mc_anneal")
+           "sdc_mc_anneal", "sdc_mc_create", "sdc_mc_run", "sdc_mc_timings", "sdc_mc_destroy")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -114,6 +114,10 @@ def lib():
         L.sdc_plan_structure_factor.argtypes = [P, P, i32, P, P, P]
         L.sdc_mc_n_sweeps.argtypes = [ctypes.POINTER(McSpec), ctypes.POINTER(i64)]
         L.sdc_mc_anneal.argtypes = [P, i64, ctypes.POINTER(McSpec), P, P, P, P, ctypes.c_int, P]
+        L.sdc_mc_create.argtypes = [P, i64, ctypes.POINTER(McSpec), ctypes.c_int, ctypes.POINTER(P)]
+        L.sdc_mc_run.argtypes = [P, ctypes.POINTER(McSpec), P, P, P, P, P]
+        L.sdc_mc_timings.argtypes = [P, P]
+        L.sdc_mc_destroy.argtypes = [P]
         L.sdc_sq_create.argtypes = [P, i64, P, i32, ctypes.POINTER(SqSpec), ctypes.c_int, ctypes.POINTER(P)]
         L.sdc_sq_accumulate.argtypes = [P, P, i64, P]
         L.sdc_sq_finalize.argtypes = [P, P, P, P]
@@ -424,6 +428,55 @@ def mc_anneal(positions, spec, init_state, state_out, device=0, stream=None, his
     if history:
         acc = acc[:mc_n_sweeps(spec)]
     return acc, float(info[0]), float(info[1]), float(info[2]), int(info[3])
+
+
+class MonteCarlo:
+    """Reusable annealed Metropolis sweeps on one sample (bonds and colour
+    classes built once)."""
+
+    def __init__(self, positions, spec, device=0):
+        self._h = None
+        pos = np.ascontiguousarray(positions, dtype=np.float32)
+        self.n_sites = pos.shape[0]
+        h = ctypes.c_void_p()
+        _check(lib().sdc_mc_create(_np_ptr(pos), self.n_sites, ctypes.byref(spec), int(device), ctypes.byref(h)),
+               "sdc_mc_create")
+        self._h = h
+
+    def run(self, schedule, state_out, init_state=None, stream=None, history=False, info=False):
+        """Run schedule's sweeps (from init_state, or from the previous run's
+        state); returns (accepted per sweep or None, info array or None)."""
+        if tuple(state_out.shape) != (self.n_sites, 3):
+            raise ValueError("states must have shape [n_sites][3]")
+        acc = np.zeros(max(mc_n_sweeps(schedule), 1), dtype=np.int64) if history else None
+        inf = np.zeros(4) if info else None
+        ip = _dev_ptr(init_state, "torch.float32") if init_state is not None else None
+        _check(lib().sdc_mc_run(self._h, ctypes.byref(schedule), ip, _dev_ptr(state_out, "torch.float32"),
+                                _np_ptr(acc) if history else None, _np_ptr(inf) if info else None,
+                                _stream_ptr(stream)), "sdc_mc_run")
+        return (acc[:mc_n_sweeps(schedule)] if history else None), inf
+
+    def timings(self):
+        ms = np.zeros(1)
+        _check(lib().sdc_mc_timings(self._h, _np_ptr(ms)), "sdc_mc_timings")
+        return float(ms[0])
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().sdc_mc_destroy(self._h), "sdc_mc_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class StructureFactor:

@@ -188,3 +188,35 @@ def test_sq_no_device_reported_on_host():
     st, h = _sq_create(inputs.ball_positions(50, 2.0, seed=3), np.zeros((1, 3)), sdc.SqSpec(4, 8, 1, 0))
     assert st == sdc.ERR_NO_DEVICE
     assert not h.value
+
+
+def test_mc_validation_codes():
+    L = sdc.lib()
+    good = sdc.mc_spec(sdc.BINS_SC, cells=(4, 4, 4), T_start=1.0, T_end=0.5, sweeps_final=2)
+    n = ctypes.c_int64()
+    assert L.sdc_mc_n_sweeps(ctypes.byref(good), ctypes.byref(n)) == sdc.OK and n.value == 7 + 2  # 1.0 .. 0.9^6
+    for field, value in [("cool", 1.0), ("cool", 0.0), ("T_end", 0.0), ("T_start", float("nan")), ("cone0", 4.0),
+                         ("acc_target", 0.7), ("sweeps_per_T", 0), ("sweeps_final", -1), ("Hz", float("inf"))]:
+        bad = sdc.mc_spec(sdc.BINS_SC, cells=(4, 4, 4), T_start=1.0, T_end=0.5, sweeps_final=2)
+        setattr(bad, field, value)
+        assert L.sdc_mc_n_sweeps(ctypes.byref(bad), ctypes.byref(n)) == sdc.ERR_INVALID_ARG, field
+    huge = sdc.mc_spec(sdc.BINS_SC, cells=(4, 4, 4), T_start=1.0, T_end=1e-300, cool=0.999999,
+                       sweeps_per_T=10 ** 9)
+    assert L.sdc_mc_n_sweeps(ctypes.byref(huge), ctypes.byref(n)) == sdc.ERR_UNSUPPORTED
+    h = ctypes.c_void_p()
+    assert L.sdc_mc_create(None, 64, ctypes.byref(good), 0, ctypes.byref(h)) == sdc.ERR_INVALID_ARG
+    assert L.sdc_mc_run(None, ctypes.byref(good), None, None, None, None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_mc_timings(None, None) == sdc.ERR_INVALID_ARG
+    assert L.sdc_mc_destroy(None) == sdc.OK
+    assert L.sdc_mc_anneal(None, 64, ctypes.byref(good), None, None, None, None, 0, None) == sdc.ERR_INVALID_ARG
+
+
+def test_mc_no_device_reported_on_host():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    pos = np.ascontiguousarray(inputs.sc_positions((4, 4, 4)))
+    good = sdc.mc_spec(sdc.BINS_SC, cells=(4, 4, 4), T_start=1.0, T_end=0.5, sweeps_final=2)
+    h = ctypes.c_void_p()
+    st = sdc.lib().sdc_mc_create(pos.ctypes.data_as(ctypes.c_void_p), 64, ctypes.byref(good), 0, ctypes.byref(h))
+    assert st == sdc.ERR_NO_DEVICE and not h.value

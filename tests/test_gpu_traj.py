@@ -305,3 +305,27 @@ def test_mc_rejects_bad_specs(torch_dev, S):
         setattr(spec, field, value)
         with pytest.raises(S.SdcError):
             S.mc_anneal(pos, spec, st, st)
+
+
+def test_mc_object_runs(torch_dev, S):
+    """The reusable object gives the one-call result bit for bit, continues
+    from its FP64 state, and times its sweeps."""
+    _say("mc object")
+    L = (6, 6, 6)
+    pos = inputs.sc_positions(L)
+    n = pos.shape[0]
+    spec = S.mc_spec(S.BINS_SC, cells=L, J=-1.0, D=0.2, Hz=0.3, seed=0x5DC0A104, T_start=1.5, T_end=0.2,
+                     cool=0.7, sweeps_per_T=4, sweeps_final=10)
+    init = torch_dev.from_numpy(inputs.random_unit_frames(1, n, seed=25)[0]).cuda()
+    one = torch_dev.zeros_like(init)
+    acc1, E1, *_ = S.mc_anneal(pos, spec, init, one)
+    with S.MonteCarlo(pos, spec) as mc:
+        with pytest.raises(S.SdcError):
+            mc.run(spec, torch_dev.zeros_like(init))  # no configuration yet
+        two = torch_dev.zeros_like(init)
+        acc2, info = mc.run(spec, two, init_state=init, history=True, info=True)
+        assert np.array_equal(acc1, acc2) and torch_dev.equal(one, two) and info[0] == E1
+        spec.seed, spec.T_start, spec.T_end, spec.sweeps_final = 0x5DC0A105, 0.2, 0.05, 20
+        three = torch_dev.zeros_like(init)
+        _, info3 = mc.run(spec, three, info=True)  # continues from the FP64 state
+        assert info3[0] < E1 and mc.timings() > 0.0

@@ -176,12 +176,21 @@ __global__ __launch_bounds__(256) void mc_out_kernel(McArgs a, float* __restrict
         out[3 * (int64_t)a.site_of[x / 3] + x % 3] = (float)a.S[x];
 }
 
-__global__ void mc_info_kernel(McArgs a, const double* __restrict__ partial, int n_partial, double T_last,
-                               double* __restrict__ info) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup: thread t sums partials t, t + 256, ... in order, then a
+// fixed tree (the same result on every run).
+__global__ __launch_bounds__(256) void mc_info_kernel(McArgs a, const double* __restrict__ partial, int n_partial,
+                                                      double T_last, double* __restrict__ info) {
+    __shared__ double red[256];
     double e = 0.0;
-    for (int b = 0; b < n_partial; ++b) e += partial[b];
-    info[0] = e / (double)a.n;
+    for (int b = threadIdx.x; b < n_partial; b += 256) e += partial[b];
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    info[0] = red[0] / (double)a.n;
     info[1] = a.cone[0];
     info[2] = T_last;
 }
@@ -222,7 +231,7 @@ int launch_mc_finish(const McArgs& a, double* partial, double T_last, float* out
     const unsigned g = grid_of(a.n);
     hipLaunchKernelGGL(mc_energy_kernel, dim3(g), dim3(256), 0, s, a, partial);
     hipLaunchKernelGGL(mc_out_kernel, dim3(grid_of(3 * a.n)), dim3(256), 0, s, a, out);
-    hipLaunchKernelGGL(mc_info_kernel, dim3(1), dim3(64), 0, s, a, (const double*)partial, (int)g, T_last, info);
+    hipLaunchKernelGGL(mc_info_kernel, dim3(1), dim3(256), 0, s, a, (const double*)partial, (int)g, T_last, info);
     return (int)hipGetLastError();
 }
 

@@ -340,8 +340,10 @@ sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const dou
  * Add one trajectory: spins_dev [n_frames][n_sites][3] fp32 device memory
  * (site order of positions_host), n_frames >= (n_origins - 1) s + n_lags,
  * read-only until the stream reaches this work.  Queued on the stream with
- * no allocation and no host synchronisation; deterministic (no atomics: the
- * partial transforms of the site ranges are summed in a fixed order).
+ * no allocation, memset or host synchronisation, so it can be captured into
+ * a graph (the origin total is counted on the device: each replay counts);
+ * deterministic (no atomics: the partial transforms of the site ranges are
+ * summed in a fixed order).
  * Calls on one accumulator must not overlap in time.
  * Errors: INVALID_ARG, STATE, HIP.
  */

@@ -233,3 +233,33 @@ def test_sq_full_size_ball65k(torch_dev, S):
     e = _err(sqt[0], ref)
     print(f"  q = 0: normwise error {e:.2e}", flush=True)
     assert e <= BAR
+
+
+def test_sq_graph_capture_replays(torch_dev, S, orc):
+    """A captured accumulate replayed three times with eager work in between:
+    after every replay S(q, t) equals the oracle's (the origin total counts
+    the replays, so the average is unchanged) and capture itself runs
+    nothing."""
+    torch = torch_dev
+    _say("sq graph capture")
+    pos = inputs.ball_positions(900, 6.0, seed=71)
+    n_o, n_L = 6, 9
+    q = _random_q(70, 2.0, seed=72)
+    fr = torch.from_numpy(inputs.random_unit_frames(n_o + n_L - 1, 900, seed=73)).to("cuda")
+    ref = orc.structure_factor_q(pos, fr.cpu().numpy(), n_o, list(range(n_L)), q)
+    with S.StructureFactor(pos, q, n_o, n_L) as sq:
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            sq.accumulate(fr)
+        torch.cuda.synchronize()
+        sqt, _ = sq.finalize()
+        assert not np.any(sqt)  # nothing accumulated by the capture
+        x = torch.randn(256, 256, device="cuda")
+        for rep in range(3):
+            g.replay()
+            y = x @ x
+            torch.cuda.synchronize()
+            assert torch.isfinite(y).all()
+            sqt, _ = sq.finalize()
+            assert _err(sqt, ref) <= BAR, rep

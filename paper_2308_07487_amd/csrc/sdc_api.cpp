@@ -107,7 +107,7 @@ struct sdc_plan {
     sdc_bin_spec bins{};
     sdc_corr_spec corr{};
     Layout lay;
-    int n_c = 0, O8 = 0, F8 = 0;
+    int nk = 0, O8 = 0, F8 = 0;
     int64_t t_req = 0;
     std::vector<void*> owned;
     int32_t* d_perm = nullptr;
@@ -218,7 +218,7 @@ sdc_status fused_args(const sdc_plan* p, const LagSel& sel, sdc::FusedArgs* a) {
     a->n_pad = L.n_pad;
     a->O8 = p->O8;
     a->F8 = p->F8;
-    a->n_c = p->n_c;
+    a->nk = p->nk;
     a->phase_stride = (int64_t)3 * p->F8 * L.n_pad;
     a->pairs = p->d_pairs;
     a->streams = p->d_streams;
@@ -447,16 +447,18 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
     p->device = device;
     const Layout& L = p->lay;
     const int sstr = corr->origin_stride;
-    p->n_c = (corr->n_origins + sdc::kKStep - 1) / sdc::kKStep;
-    p->O8 = 2 * p->n_c;
+    p->O8 = (corr->n_origins + sdc::kOriginBlock - 1) / sdc::kOriginBlock;
+    p->nk = (3 * p->O8 + 1) / 2;
     const int u_max = (corr->n_lags - 1) / sstr;
     const int lg = sdc::lag_group(corr->precision);
     const int u0_max = (u_max / lg) * lg;
-    // largest block read: 2(n_c - 1) + 1 (half) + u0_max / 8 + win_blocks - 1
-    p->F8 = 2 * p->n_c + u0_max / 8 + sdc::win_blocks(lg) - 1;
+    // largest block read: (O8 - 1) + u0_max / 8 + win_blocks - 1
+    p->F8 = p->O8 + u0_max / 8 + sdc::win_blocks(lg) - 1;
     p->t_req = (int64_t)(corr->n_origins - 1) * sstr + corr->n_lags;
     const size_t elem = corr->precision == SDC_PREC_BF16X3 ? 48 : 32;  // bytes per pack element
-    p->bytes_A = (size_t)3 * p->O8 * L.n_pad * elem;
+    // A: [3][O8] blocks plus one zero block, read by the lane half past the
+    // last block when 3 O8 is odd
+    p->bytes_A = ((size_t)3 * p->O8 + 1) * L.n_pad * elem;
     p->bytes_B = (size_t)sstr * 3 * p->F8 * L.n_pad * elem;
     if (sdc::fused_lds_bytes(L.win, corr->precision) > sdc::kMaxFusedLds) {
         delete p;
@@ -521,6 +523,7 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
            "upload streams");
     if (corr->flags & SDC_FLAG_TIMING)
         for (int k = 0; k < 4; ++k) TRYHIP(hipEventCreate(&p->ev[k]), "hipEventCreate");
+    TRYHIP(hipMemset(p->d_A, 0, p->bytes_A), "zero A pack");
     TRYHIP(hipMemset(p->d_counts, 0, (size_t)L.n_bins * 8), "zero counts");
     TRYHIP(hipMemset(p->d_H, 0, (size_t)corr->n_lags * L.n_bins * 8), "zero H");
     TRYHIP(hipMemset(p->d_self, 0, (size_t)corr->n_lags * 8), "zero self");

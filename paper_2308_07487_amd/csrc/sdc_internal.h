@@ -29,8 +29,10 @@ constexpr bool one_wg_per_cu(int precision) {
 constexpr int lag_group(int precision) { return precision == SDC_PREC_FP32 ? 16 : 8; }
 // Pack elements (8 samples each) in one lane's B window: LG - 1 + 8 samples.
 constexpr int win_blocks(int lg) { return (lg + 14) / 8; }
-// Origins per K-step of the fused product (two blocks of 8).
-constexpr int kKStep = 16;
+// Origins per pack block; a K-step of the fused product takes two blocks
+// (one per lane half of the 32x32 MFMA), running over the blocks of all three
+// components in turn.
+constexpr int kOriginBlock = 8;
 
 // One tile pair of a stream: i-tile, j-tile and the window shift of this pair.
 struct KPair {
@@ -156,7 +158,8 @@ struct FusedArgs {
     const void* A;
     const void* B;
     int64_t n_pad;
-    int O8, F8, n_c;
+    int O8, F8;                    // origin blocks per component (A), window blocks (B)
+    int nk;                        // K-steps: ceil(3 O8 / 2)
     int64_t phase_stride;          // elements of 32 B per B phase
     const KPair* pairs;
     const KStream* streams;

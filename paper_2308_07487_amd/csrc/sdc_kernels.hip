@@ -352,7 +352,11 @@ int fused_lds_bytes(int win, int precision) {
 // One task of a plan: the stream's tile pairs for one lag group, histogram
 // in LDS (`hist`: [LG][win] FP64, then the radial edge table), merged into
 // the plan's global bins at the end.  Called by the whole workgroup.
-template <int PREC, int RADIAL>
+// PAIRED: O8 is even, so a K-step's two origin blocks always lie in one
+// component and the block offsets follow from the step with one scalar
+// division; otherwise the blocks of all components are taken in turn and a
+// step may straddle two components.
+template <int PREC, int RADIAL, int PAIRED>
 __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double* hist) {
     constexpr int LG = lag_group(PREC);
     constexpr int NB = win_blocks(LG);
@@ -372,8 +376,14 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
     using Elem = PackElem<PREC>;
     const Elem* Ab = (const Elem*)a.A;
     const Elem* Bb = (const Elem*)a.B + (int64_t)grp.phase * a.phase_stride;
-    const int nk = 3 * a.n_c;
+    // K-steps run over the 3 O8 origin blocks of all components, two blocks
+    // per step (one per lane half); a half past the last block reads the A
+    // pack's zero block 3 O8
+    const int nk = a.nk;
+    const int nblk = 3 * a.O8;
     const int ublk = grp.u0 / 8;
+    const int dF = a.F8 - a.O8;  // B block of A block k (component c): k + c dF + ublk
+    const int n_c = a.O8 / 2;    // PAIRED: K-steps per component
 
     for (int p = st.p0; p < st.p1; ++p) {
         const KPair pr = a.pairs[p];
@@ -391,27 +401,32 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
                 for (int r = 0; r < 16; ++r) acc.s[m][r] = 0.0f;
         }
 
-        auto addrA = [&](int kk) {
-            const int alpha = kk / a.n_c, c = kk - alpha * a.n_c;
-            return Ab + ((int64_t)(alpha * a.O8 + 2 * c + h)) * a.n_pad + si;
-        };
-        auto addrB = [&](int kk) {
-            const int alpha = kk / a.n_c, c = kk - alpha * a.n_c;
-            return Bb + ((int64_t)(alpha * a.F8 + 2 * c + h + ublk)) * a.n_pad + sj;
-        };
         // Register buffers: while K-step kk is multiplied the loads of later
-        // steps are in flight (indices clamp to the last step).
+        // steps are in flight (indices clamp to the last block).
         auto load = [&](Stage<PREC, NB>& b, int kk) {
             kk = kk < nk ? kk : nk - 1;
-            b.a = *addrA(kk);
-            const Elem* pb = addrB(kk);
+            const Elem* pb;
+            if constexpr (PAIRED) {
+                const int alpha = kk / n_c, c = kk - alpha * n_c;
+                b.a = Ab[(int64_t)(alpha * a.O8 + 2 * c + h) * a.n_pad + si];
+                pb = Bb + (int64_t)(alpha * a.F8 + 2 * c + h + ublk) * a.n_pad + sj;
+            } else {
+                // block indices of both lane halves from the step index
+                // (uniform); A: [3][O8] blocks flattened, then the zero block
+                const int k0 = 2 * kk;
+                const int k1 = k0 + 1 < nblk ? k0 + 1 : nblk - 1;
+                const int b0 = k0 + ((k0 >= a.O8) + (k0 >= 2 * a.O8)) * dF + ublk;
+                const int b1 = k1 + ((k1 >= a.O8) + (k1 >= 2 * a.O8)) * dF + ublk;
+                b.a = Ab[(int64_t)(k0 + h) * a.n_pad + si];
+                pb = Bb + (int64_t)(h ? b1 : b0) * a.n_pad + sj;
+            }
 #pragma unroll
             for (int q = 0; q < NB; ++q) b.b[q] = pb[q * a.n_pad];
         };
         if constexpr (one_wg_per_cu(PREC)) {
             // One wave per SIMD: three buffers keep two K-steps of loads in
-            // flight.  nk = 3 * n_c is a multiple of 3, so the rotation needs
-            // no tail; the scheduling barriers keep loads ahead of the MFMAs.
+            // flight (the last round stops at nk); the scheduling barriers
+            // keep loads ahead of the MFMAs.
             Stage<PREC, NB> s0, s1, s2;
             load(s0, 0);
             load(s1, 1);
@@ -422,11 +437,11 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
                 __builtin_amdgcn_sched_barrier(0);
                 load(s0, kk + 3);
                 __builtin_amdgcn_sched_barrier(0);
-                stage_mma<PREC, NB, LG>(s1, acc);
+                if (kk + 1 < nk) stage_mma<PREC, NB, LG>(s1, acc);
                 __builtin_amdgcn_sched_barrier(0);
                 load(s1, kk + 4);
                 __builtin_amdgcn_sched_barrier(0);
-                stage_mma<PREC, NB, LG>(s2, acc);
+                if (kk + 2 < nk) stage_mma<PREC, NB, LG>(s2, acc);
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
@@ -521,7 +536,7 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
     }
 }
 
-template <int PREC, int RADIAL>
+template <int PREC, int RADIAL, int PAIRED>
 __global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_kernel(FusedArgs a) {
     extern __shared__ double hist[];
     // XCD-aware task order: consecutive tasks land on the same XCD (work-
@@ -533,7 +548,7 @@ __global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_kernel
     const int per = (n_tasks + 7) / 8;
     const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (task >= n_tasks) return;
-    fused_task<PREC, RADIAL>(a, task, hist);
+    fused_task<PREC, RADIAL, PAIRED>(a, task, hist);
 }
 
 // Persistent kernel over the tasks of several plans (one launch for a
@@ -592,7 +607,7 @@ __global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_batch_
         const int pl = __builtin_amdgcn_readfirstlane(s_plan);
         __syncthreads();
         if (task < 0) break;
-        fused_task<PREC, RADIAL>(args[pl], task, hist);
+        fused_task<PREC, RADIAL, 0>(args[pl], task, hist);  // plans of a batch differ in O8
         __syncthreads();  // the histogram is reused by the next task
     }
 }
@@ -602,10 +617,18 @@ static int launch_fused_prec(const FusedArgs& a, hipStream_t s) {
     const int lds = fused_lds_bytes(a.win, PREC);
     const int n_tasks = a.n_groups * a.n_streams;
     const int grid = 8 * ((n_tasks + 7) / 8);
-    if (a.kind == SDC_BINS_RADIAL)
-        hipLaunchKernelGGL((fused_kernel<PREC, 1>), dim3(grid), dim3(256), lds, s, a);
-    else
-        hipLaunchKernelGGL((fused_kernel<PREC, 0>), dim3(grid), dim3(256), lds, s, a);
+    const bool paired = a.O8 % 2 == 0;
+    if (a.kind == SDC_BINS_RADIAL) {
+        if (paired)
+            hipLaunchKernelGGL((fused_kernel<PREC, 1, 1>), dim3(grid), dim3(256), lds, s, a);
+        else
+            hipLaunchKernelGGL((fused_kernel<PREC, 1, 0>), dim3(grid), dim3(256), lds, s, a);
+    } else {
+        if (paired)
+            hipLaunchKernelGGL((fused_kernel<PREC, 0, 1>), dim3(grid), dim3(256), lds, s, a);
+        else
+            hipLaunchKernelGGL((fused_kernel<PREC, 0, 0>), dim3(grid), dim3(256), lds, s, a);
+    }
     return (int)hipGetLastError();
 }
 
@@ -1019,10 +1042,14 @@ int launch_self(const SelfArgs& a, void* stream) {
 // calls (they stay legal under stream capture).
 int prepare_kernels() {
     const void* fused[] = {
-        (const void*)fused_kernel<SDC_PREC_FP32, 0>,        (const void*)fused_kernel<SDC_PREC_FP32, 1>,
-        (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0>,  (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1>,
-        (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0>,  (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1>,
-        (const void*)fused_kernel<SDC_PREC_BF16X3, 0>,      (const void*)fused_kernel<SDC_PREC_BF16X3, 1>,
+        (const void*)fused_kernel<SDC_PREC_FP32, 0, 0>,       (const void*)fused_kernel<SDC_PREC_FP32, 1, 0>,
+        (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0, 0>, (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1, 0>,
+        (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0, 0>, (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1, 0>,
+        (const void*)fused_kernel<SDC_PREC_BF16X3, 0, 0>,     (const void*)fused_kernel<SDC_PREC_BF16X3, 1, 0>,
+        (const void*)fused_kernel<SDC_PREC_FP32, 0, 1>,       (const void*)fused_kernel<SDC_PREC_FP32, 1, 1>,
+        (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0, 1>, (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1, 1>,
+        (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0, 1>, (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1, 1>,
+        (const void*)fused_kernel<SDC_PREC_BF16X3, 0, 1>,     (const void*)fused_kernel<SDC_PREC_BF16X3, 1, 1>,
         batch_fn<SDC_PREC_FP32, 0>(),                       batch_fn<SDC_PREC_FP32, 1>(),
         batch_fn<SDC_PREC_SPLIT_BF16, 0>(),                 batch_fn<SDC_PREC_SPLIT_BF16, 1>(),
         batch_fn<SDC_PREC_SPLIT_FP16, 0>(),                 batch_fn<SDC_PREC_SPLIT_FP16, 1>(),

@@ -195,24 +195,36 @@ __global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransform
         acc_re[b] = f64x4{0.0, 0.0, 0.0, 0.0};
         acc_im[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
+    // this lane's first phase and spin in a buffer: A[i][k] = phase of wave
+    // vector i at site k sits in lane i + 16 k, B[k][c] = spin column c at
+    // site k in lane c + 16 k
+    const int a_off = (lane >> 4) * kSqQ + 16 * wave + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < kSqCB; ++b) boff[b] += 3 * (lane >> 4);
     __syncthreads();  // the first chunk is staged
     int cur = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kSqSites) {
         if (active) {
-            const double* ph = lds + cur * kSqPhBuf;
+            const double* ph = lds + cur * kSqPhBuf + a_off;
             const double* sb = lds + 2 * kSqPhBuf + cur * kSqSbBuf;
-#pragma unroll 2
-            for (int k4 = 0; k4 < kSqSites; k4 += 4) {
-                // A[i][k] = phase of wave vector i at site k: lane i + 16 k;
-                // B[k][c] = spin column c at site k: lane c + 16 k
-                const int s = k4 + (lane >> 4);
-                const double are = ph[s * kSqQ + 16 * wave + (lane & 15)];
-                const double aim = ph[kSqSites * kSqQ + s * kSqQ + 16 * wave + (lane & 15)];
+            // Two register sets: the operands of K-step k + 1 are read from
+            // LDS while the MFMAs of step k run.
+            double are[2], aim[2], bv[2][kSqCB];
+            auto fetch = [&](int k, int r) {
+                are[r] = ph[4 * k * kSqQ];
+                aim[r] = ph[kSqSites * kSqQ + 4 * k * kSqQ];
+#pragma unroll
+                for (int b = 0; b < kSqCB; ++b) bv[r][b] = sb[boff[b] + 12 * k];
+            };
+            fetch(0, 0);
+#pragma unroll
+            for (int k = 0; k < kSqSites / 4; ++k) {
+                const int r = k & 1;
+                if (k + 1 < kSqSites / 4) fetch(k + 1, r ^ 1);
 #pragma unroll
                 for (int b = 0; b < kSqCB; ++b) {
-                    const double bv = sb[boff[b] + 3 * s];
-                    acc_re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv, acc_re[b], 0, 0, 0);
-                    acc_im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bv, acc_im[b], 0, 0, 0);
+                    acc_re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[r], bv[r][b], acc_re[b], 0, 0, 0);
+                    acc_im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[r], bv[r][b], acc_im[b], 0, 0, 0);
                 }
             }
         }

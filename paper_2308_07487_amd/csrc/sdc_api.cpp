@@ -1019,7 +1019,7 @@ struct sdc_sq {
     std::vector<void*> owned;
     float* d_pos = nullptr;
     double* d_q = nullptr;
-    double* d_pack = nullptr;  // [ceil(n / 32)][t_pad][32][3] packed spins
+    double* d_pack = nullptr;  // [ceil(n / chunk)][t_pad][chunk][3] packed spins (chunk = sq_site_chunk())
     double* d_part = nullptr;  // [n_split][n_q][2][3 t_used]
     double* d_F = nullptr;     // [n_q][t_used][3][2]
     double* d_raw = nullptr;   // [n_q][n_lags][2]
@@ -1092,19 +1092,34 @@ sdc_status sdc_sq_create(const float* positions_host, int64_t n_sites, const dou
     const int fb = sdc::sq_frames_per_block();
     q->t_pad = (q->t_used + fb - 1) / fb * fb;
     const int64_t n_cols = 3 * (int64_t)q->t_used;
-    // Site ranges: enough workgroups to fill the chip (about 2048), at least
-    // four staged chunks per range, partials within kMaxSqPartBytes.
+    // Site ranges: enough workgroups to fill the chip (one per compute unit
+    // at a time; 1536 to 3072 of them, the count that leaves the last round
+    // of the chip fullest), at least four staged chunks per range, partials
+    // within kMaxSqPartBytes.
     const int64_t chunk = sdc::sq_site_chunk();
     const int64_t tiles = sdc::sq_tiles_per_split(n_q, q->t_used);
     const size_t per_split = (size_t)n_q * 2 * n_cols * sizeof(double);
-    int64_t split = (2048 + tiles - 1) / tiles;
-    split = std::min<int64_t>(split, std::max<int64_t>(1, n_sites / (4 * chunk)));
-    split = std::min<int64_t>(split, std::max<int64_t>(1, (int64_t)(kMaxSqPartBytes / per_split)));
-    split = std::max<int64_t>(1, std::min<int64_t>(split, 65535));
-    int64_t sps = (n_sites + split - 1) / split;
-    sps = (sps + chunk - 1) / chunk * chunk;
-    q->sites_per_split = sps;
-    q->n_split = (int)((n_sites + sps - 1) / sps);
+    int n_cu = 256;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu < 1)
+        n_cu = 256;
+    const int64_t split_cap = std::max<int64_t>(1, std::min<int64_t>({n_sites / (4 * chunk),
+        (int64_t)(kMaxSqPartBytes / per_split), 65535}));
+    int64_t best_sps = 0, best_split = 0;
+    double best_fill = -1.0;
+    for (int64_t s = std::max<int64_t>(1, 1536 / tiles); s <= std::max<int64_t>(1, 3072 / tiles); ++s) {
+        int64_t sps = (n_sites + std::min(s, split_cap) - 1) / std::min(s, split_cap);
+        sps = (sps + chunk - 1) / chunk * chunk;
+        const int64_t ns = (n_sites + sps - 1) / sps;
+        const int64_t wg = tiles * ns, rounds = (wg + n_cu - 1) / n_cu;
+        const double fill = (double)wg / (double)(rounds * n_cu);
+        if (fill > best_fill + 1e-9) {
+            best_fill = fill;
+            best_sps = sps;
+            best_split = ns;
+        }
+    }
+    q->sites_per_split = best_sps;
+    q->n_split = (int)best_split;
     const size_t out_n = (size_t)n_q * spec->n_lags * 2;
 #define SQ_TRY(x)               \
     do {                        \

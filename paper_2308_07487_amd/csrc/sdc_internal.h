@@ -278,7 +278,7 @@ int launch_sqw(const double* sqt, double* sqw, int n_q, int n_lags, void* stream
 // q-resolved S(q, t) of Eq. (3) at arbitrary wave vectors (sdc_sq.hip).
 struct SqTransformArgs {
     const float* frames;      // [>= n_frames_used][n][3] fp32, caller's site order (pack input)
-    double* packed;           // [ceil(n / 32)][t_pad][32][3] FP64 (pack output, contraction input)
+    double* packed;           // [ceil(n / chunk)][t_pad][chunk][3] FP64, chunk = sq_site_chunk() (pack output, contraction input)
     int t_pad;                // n_frames_used rounded up to whole 48-frame column blocks
     const float* pos;         // [n][3] fp32
     const double* q;          // [n_q][3]

@@ -58,29 +58,34 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
     *c = ((q + 1) & 2) ? -c0 : c0;
 }
 
-constexpr int kSqWaves = 4;                 // consumer waves (MFMA); as many producer waves
-constexpr int kSqThreads = 2 * 64 * kSqWaves;
-constexpr int kSqQ = 16 * kSqWaves;         // wave vectors per workgroup: one 16-row block per consumer
-constexpr int kSqSites = 32;                // sites per chunk (8 MFMA K-steps of 4)
-constexpr int kSqCB = 9;                    // 16-column blocks, shared by the consumers
-constexpr int kSqCols = kSqCB * 16;         // 144 spin-matrix columns = 48 whole frames
+constexpr int kSqQBlocks = 4;               // 16-row wave-vector blocks per workgroup
+constexpr int kSqHalves = 2;                // column ranges per wave-vector block
+constexpr int kSqWaves = kSqQBlocks * kSqHalves;  // consumer waves (MFMA), two per SIMD
+constexpr int kSqProdWaves = 4;             // producer waves, one per SIMD
+constexpr int kSqThreads = 64 * (kSqWaves + kSqProdWaves);
+constexpr int kSqQ = 16 * kSqQBlocks;       // wave vectors per workgroup
+constexpr int kSqSites = 24;                // sites per chunk (6 MFMA K-steps of 4)
+constexpr int kSqCB = 12;                   // 16-column blocks per workgroup
+constexpr int kSqCBW = kSqCB / kSqHalves;   // 16-column blocks per consumer wave
+constexpr int kSqCols = kSqCB * 16;         // 192 spin-matrix columns = 64 whole frames
 constexpr int kSqFrames = kSqCols / 3;
 constexpr int kSqPitch = 3 * kSqSites + 4;  // LDS doubles per staged frame (padded against bank conflicts)
 constexpr int kSqPhBuf = 2 * kSqSites * kSqQ;    // doubles of one phase buffer (cos, -sin)
 constexpr int kSqSbBuf = kSqFrames * kSqPitch;   // doubles of one spin buffer
 constexpr int kSqLdsBytes = 2 * (kSqPhBuf + kSqSbBuf) * (int)sizeof(double);
 static_assert(kSqCols % 3 == 0, "a column range must cover whole frames");
+static_assert(kSqCB % kSqHalves == 0 && kSqSites % 4 == 0, "consumer split");
 static_assert(kSqLdsBytes <= 160 * 1024, "two chunk buffers must fit in LDS");
 
-constexpr int kSqProducers = 64 * kSqWaves;
+constexpr int kSqProducers = 64 * kSqProdWaves;
 constexpr int kSqPhPer = kSqSites * kSqQ / kSqProducers;         // phases per producer thread
 constexpr int kSqSbPer = kSqFrames * 3 * kSqSites / kSqProducers;  // spin values per producer thread
 static_assert(kSqPhPer * kSqProducers == kSqSites * kSqQ && kSqProducers % kSqQ == 0, "phase split");
 static_assert(kSqSbPer * kSqProducers == kSqFrames * 3 * kSqSites && kSqSbPer % 2 == 0, "spin split");
 static_assert(kSqPitch % 2 == 0, "16-byte LDS rows");
 
-// Producer side: the phases of the 64 wave vectors at the 32 sites of chunk
-// j0 and the chunk's spins of 48 frames (one contiguous FP64 block of the
+// Producer side: the phases of the 64 wave vectors at the 24 sites of chunk
+// j0 and the chunk's spins of 64 frames (one contiguous FP64 block of the
 // packed spins) into one buffer.  Producer thread p keeps wave vector p % 64
 // (qv, zero past n_q) and takes sites p / 64 + 4 i; every global load of the
 // chunk is issued before the first is used.
@@ -96,7 +101,7 @@ __device__ __forceinline__ void sq_produce(const SqTransformArgs& a, int ptid, c
         py[i] = in ? a.pos[3 * j + 1] : 0.0f;
         pz[i] = in ? a.pos[3 * j + 2] : 0.0f;
     }
-    // the chunk's 48 frames x 32 sites x 3 components, as pairs of doubles
+    // the chunk's 64 frames x 24 sites x 3 components, as pairs of doubles
     const double2* src =
         (const double2*)(a.packed + ((j0 / kSqSites) * a.t_pad + f_first) * (3 * kSqSites));
     double2 v[kSqSbPer / 2];
@@ -116,15 +121,15 @@ __device__ __forceinline__ void sq_produce(const SqTransformArgs& a, int ptid, c
     }
 #pragma unroll
     for (int i = 0; i < kSqSbPer / 2; ++i) {
-        const int e = ptid + kSqProducers * i;  // pair index: frame e / 48, values 2 (e % 48), +1
+        const int e = ptid + kSqProducers * i;  // pair index: frame e / 36, values 2 (e % 36), +1
         const int fl = e / (3 * kSqSites / 2), r = 2 * (e - fl * (3 * kSqSites / 2));
         *(double2*)(sb + fl * kSqPitch + r) = v[i];
     }
 }
 
-// Packed spins for the contraction: P[c][f][s][a] = S_j^a(f), j = 32 c + s,
+// Packed spins for the contraction: P[c][f][s][a] = S_j^a(f), j = 24 c + s,
 // FP64, zero for sites past N and frames past n_frames_used (t_pad frames
-// per chunk, a multiple of 48), so that a chunk's 48 frames are one
+// per chunk, a multiple of 64), so that a block's 64 frames are one
 // contiguous block.
 __global__ __launch_bounds__(256) void sq_pack_kernel(SqTransformArgs a) {
     const int64_t per_chunk = (int64_t)a.t_pad * 3 * kSqSites;
@@ -138,14 +143,17 @@ __global__ __launch_bounds__(256) void sq_pack_kernel(SqTransformArgs a) {
     }
 }
 
-// One workgroup: 64 wave vectors x 144 columns (48 frames x 3 components) x
-// one range of sites, in chunks of 32 sites with two LDS buffers.  Four
-// producer waves fill the next chunk's buffer (64 x 32 phases, cos and -sin
-// of q.r in FP64, and the spins) while four consumer waves run the current
-// chunk: consumer w takes its 16 wave vectors through 8 K-steps of 4 sites,
-// two FP64 MFMAs (real and imaginary phase rows) per 16-column block sharing
-// the spin operand.  One barrier per chunk.  Spins are read from memory once
-// per 64 wave vectors and each phase is computed once per 144 columns.  The
+// One workgroup: 64 wave vectors x 192 columns (64 frames x 3 components) x
+// one range of sites, in chunks of 24 sites with two LDS buffers.  Four
+// producer waves fill the next chunk's buffer (64 x 24 phases, cos and -sin
+// of q.r in FP64, and the spins) while eight consumer waves, two per SIMD so
+// that one issues MFMAs while the other waits, run the current chunk:
+// consumer w takes wave vectors 16 (w % 4) .. +15 and column blocks
+// 6 (w / 4) .. +5 through 6 K-steps of 4 sites, two FP64 MFMAs (real and
+// imaginary phase rows) per 16-column block sharing the spin operand.  One
+// barrier per chunk.  Spins are read from memory once per 64 wave vectors and
+// each phase is computed once per 192 columns (the FP64 vector work of the
+// phases takes issue cycles from the FP64 MFMAs).  The
 // partial transform of the site range goes to its own slice of `part` (no
 // atomics; the slices are summed in a fixed order).
 __global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransformArgs a) {
@@ -181,26 +189,27 @@ __global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransform
         }
         return;
     }
-    const bool active = q0 + 16 * wave < a.n_q;  // wave-uniform
+    const int qb = wave % kSqQBlocks, cb0 = (wave / kSqQBlocks) * kSqCBW;
+    const bool active = q0 + 16 * qb < a.n_q;  // wave-uniform
     // LDS offset of this lane's column in each block (frame row, component)
-    int boff[kSqCB];
+    int boff[kSqCBW];
 #pragma unroll
-    for (int b = 0; b < kSqCB; ++b) {
-        const int c = b * 16 + (lane & 15);
+    for (int b = 0; b < kSqCBW; ++b) {
+        const int c = (cb0 + b) * 16 + (lane & 15);
         boff[b] = (c / 3) * kSqPitch + c % 3;
     }
-    f64x4 acc_re[kSqCB], acc_im[kSqCB];
+    f64x4 acc_re[kSqCBW], acc_im[kSqCBW];
 #pragma unroll
-    for (int b = 0; b < kSqCB; ++b) {
+    for (int b = 0; b < kSqCBW; ++b) {
         acc_re[b] = f64x4{0.0, 0.0, 0.0, 0.0};
         acc_im[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
     // this lane's first phase and spin in a buffer: A[i][k] = phase of wave
     // vector i at site k sits in lane i + 16 k, B[k][c] = spin column c at
     // site k in lane c + 16 k
-    const int a_off = (lane >> 4) * kSqQ + 16 * wave + (lane & 15);
+    const int a_off = (lane >> 4) * kSqQ + 16 * qb + (lane & 15);
 #pragma unroll
-    for (int b = 0; b < kSqCB; ++b) boff[b] += 3 * (lane >> 4);
+    for (int b = 0; b < kSqCBW; ++b) boff[b] += 3 * (lane >> 4);
     __syncthreads();  // the first chunk is staged
     int cur = 0;
     for (int64_t j0 = jb; j0 < je; j0 += kSqSites) {
@@ -209,12 +218,12 @@ __global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransform
             const double* sb = lds + 2 * kSqPhBuf + cur * kSqSbBuf;
             // Two register sets: the operands of K-step k + 1 are read from
             // LDS while the MFMAs of step k run.
-            double are[2], aim[2], bv[2][kSqCB];
+            double are[2], aim[2], bv[2][kSqCBW];
             auto fetch = [&](int k, int r) {
                 are[r] = ph[4 * k * kSqQ];
                 aim[r] = ph[kSqSites * kSqQ + 4 * k * kSqQ];
 #pragma unroll
-                for (int b = 0; b < kSqCB; ++b) bv[r][b] = sb[boff[b] + 12 * k];
+                for (int b = 0; b < kSqCBW; ++b) bv[r][b] = sb[boff[b] + 12 * k];
             };
             fetch(0, 0);
 #pragma unroll
@@ -222,7 +231,7 @@ __global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransform
                 const int r = k & 1;
                 if (k + 1 < kSqSites / 4) fetch(k + 1, r ^ 1);
 #pragma unroll
-                for (int b = 0; b < kSqCB; ++b) {
+                for (int b = 0; b < kSqCBW; ++b) {
                     acc_re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[r], bv[r][b], acc_re[b], 0, 0, 0);
                     acc_im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[r], bv[r][b], acc_im[b], 0, 0, 0);
                 }
@@ -237,11 +246,11 @@ __global__ __launch_bounds__(kSqThreads, 1) void sq_transform_kernel(SqTransform
     // FP32 forms)
     double* out = a.part + (int64_t)blockIdx.z * a.n_q * 2 * n_cols;
 #pragma unroll
-    for (int b = 0; b < kSqCB; ++b) {
-        const int64_t c = c0 + b * 16 + (lane & 15);
+    for (int b = 0; b < kSqCBW; ++b) {
+        const int64_t c = c0 + (cb0 + b) * 16 + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int qq = q0 + 16 * wave + 4 * v + (lane >> 4);
+            const int qq = q0 + 16 * qb + 4 * v + (lane >> 4);
             if (qq < a.n_q && c < n_cols) {
                 out[(int64_t)qq * 2 * n_cols + c] = acc_re[b][v];
                 out[((int64_t)qq * 2 + 1) * n_cols + c] = acc_im[b][v];

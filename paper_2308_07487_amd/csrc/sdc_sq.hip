@@ -59,14 +59,14 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
 }
 
 constexpr int kSqQBlocks = 4;               // 16-row wave-vector blocks per workgroup
-constexpr int kSqHalves = 2;                // column ranges per wave-vector block
-constexpr int kSqWaves = kSqQBlocks * kSqHalves;  // consumer waves (MFMA), two per SIMD
+constexpr int kSqColParts = 3;              // column ranges per wave-vector block
+constexpr int kSqWaves = kSqQBlocks * kSqColParts;  // consumer waves (MFMA), three per SIMD
 constexpr int kSqProdWaves = 4;             // producer waves, one per SIMD
 constexpr int kSqThreads = 64 * (kSqWaves + kSqProdWaves);
 constexpr int kSqQ = 16 * kSqQBlocks;       // wave vectors per workgroup
 constexpr int kSqSites = 24;                // sites per chunk (6 MFMA K-steps of 4)
 constexpr int kSqCB = 12;                   // 16-column blocks per workgroup
-constexpr int kSqCBW = kSqCB / kSqHalves;   // 16-column blocks per consumer wave
+constexpr int kSqCBW = kSqCB / kSqColParts;   // 16-column blocks per consumer wave
 constexpr int kSqCols = kSqCB * 16;         // 192 spin-matrix columns = 64 whole frames
 constexpr int kSqFrames = kSqCols / 3;
 constexpr int kSqPitch = 3 * kSqSites + 4;  // LDS doubles per staged frame (padded against bank conflicts)
@@ -74,7 +74,7 @@ constexpr int kSqPhBuf = 2 * kSqSites * kSqQ;    // doubles of one phase buffer 
 constexpr int kSqSbBuf = kSqFrames * kSqPitch;   // doubles of one spin buffer
 constexpr int kSqLdsBytes = 2 * (kSqPhBuf + kSqSbBuf) * (int)sizeof(double);
 static_assert(kSqCols % 3 == 0, "a column range must cover whole frames");
-static_assert(kSqCB % kSqHalves == 0 && kSqSites % 4 == 0, "consumer split");
+static_assert(kSqCB % kSqColParts == 0 && kSqSites % 4 == 0, "consumer split");
 static_assert(kSqLdsBytes <= 160 * 1024, "two chunk buffers must fit in LDS");
 
 constexpr int kSqProducers = 64 * kSqProdWaves;
@@ -146,10 +146,10 @@ __global__ __launch_bounds__(256) void sq_pack_kernel(SqTransformArgs a) {
 // One workgroup: 64 wave vectors x 192 columns (64 frames x 3 components) x
 // one range of sites, in chunks of 24 sites with two LDS buffers.  Four
 // producer waves fill the next chunk's buffer (64 x 24 phases, cos and -sin
-// of q.r in FP64, and the spins) while eight consumer waves, two per SIMD so
-// that one issues MFMAs while the other waits, run the current chunk:
+// of q.r in FP64, and the spins) while twelve consumer waves, three per SIMD so
+// that one issues MFMAs while the others wait, run the current chunk:
 // consumer w takes wave vectors 16 (w % 4) .. +15 and column blocks
-// 6 (w / 4) .. +5 through 6 K-steps of 4 sites, two FP64 MFMAs (real and
+// 4 (w / 4) .. +3 through 6 K-steps of 4 sites, two FP64 MFMAs (real and
 // imaginary phase rows) per 16-column block sharing the spin operand.  One
 // barrier per chunk.  Spins are read from memory once per 64 wave vectors and
 // each phase is computed once per 192 columns (the FP64 vector work of the

@@ -54,9 +54,9 @@ def _random_q(n_q, qmax, seed):
 
 
 @pytest.mark.parametrize("n,n_q,n_o,n_L,stride", [
-    (700, 37, 5, 7, 1),      # 22 site chunks with a ragged tail, 3 wave-vector blocks (ragged)
-    (300, 16, 40, 60, 1),    # 297 spin columns: two column groups, the second ragged
-    (2000, 3, 3, 4, 2),      # 13 site ranges, the last one partial; origin stride 2
+    (700, 37, 5, 7, 1),      # 30 site chunks of 24 with a ragged tail, 3 wave-vector blocks (ragged)
+    (300, 16, 40, 60, 1),    # 297 spin columns: two 192-column groups, the second ragged
+    (2000, 3, 3, 4, 2),      # 17 site ranges of 120, the last one partial; origin stride 2
     (1, 5, 4, 6, 3),         # a single site
 ])
 def test_sq_matches_oracle_ball(torch_dev, S, orc, n, n_q, n_o, n_L, stride):

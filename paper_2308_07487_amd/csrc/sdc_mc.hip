@@ -30,9 +30,15 @@ constexpr int kMcCounterStride = 16;  // u64 words between counters
 // half-angle `cone` about S_i (cos a uniform in [cos cone, 1], azimuth
 // uniform), Metropolis acceptance at temperature T.  Counter = (i low,
 // sweep low, i high, 2^31 | sweep high), key = seed: u_k = (w_k + 1/2) 2^-32.
+// Workgroups go to the 8 XCDs in turn; workgroup b takes block
+// x q + min(x, r) + b / 8 of the class (x = b mod 8, nb = 8 q + r blocks), so
+// each XCD sweeps one contiguous stretch of slots in order and its L2 keeps
+// the neighbour planes that the following slots read again.
 __global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, int64_t k0, int64_t count, double T,
                                                         int64_t sweep) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = gridDim.x, q = nb / 8, r = nb % 8, x = blockIdx.x % 8;
+    const int64_t lb = x * q + (x < r ? x : r) + blockIdx.x / 8;
+    const int64_t t = lb * blockDim.x + threadIdx.x;
     bool accepted = false;
     if (t < count) {
         const int64_t k = k0 + t;           // slot

@@ -229,13 +229,16 @@ def _f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("kind", ["sc", "bcc", "radial"])
-def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind):
+@pytest.mark.parametrize("kind,L", [("sc", (4, 6, 5)), ("bcc", (3, 4, 4)), ("radial", None),
+                                    ("sc", (24, 24, 20))])
+def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind, L):
     """Annealed Metropolis sweeps with every term of Eq. (1): the GPU's colour
     classes, Philox moves and cone adaptation against the oracle's on the
     same bonds (fp32 tables, as the library builds them).  Accepted moves per
-    sweep agree exactly; the states agree to the fp32 output."""
-    _say(f"mc anneal {kind}")
+    sweep agree exactly; the states agree to the fp32 output.  The 24x24x20
+    box has 5760 sites per colour class: 23 workgroups per class, spread over
+    the XCDs in unequal stretches (3 for seven of them, 2 for the last)."""
+    _say(f"mc anneal {kind} {L}")
     D, A, Hz, seed = 0.3, 0.2, 0.4, 0x5DC0A101
     if kind == "radial":
         pos = inputs.ball_positions(300, 3.0, seed=9)
@@ -244,7 +247,6 @@ def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind):
         Dv = D * rij / np.linalg.norm(rij, axis=1, keepdims=True)
         spec = S.mc_spec(S.BINS_RADIAL, coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5, J=1.0)
     else:
-        L = (4, 6, 5) if kind == "sc" else (3, 4, 4)
         pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
         sign = 0x5DC0A102 if kind == "bcc" else None
         row, col, Jv = _nn_csr(pos, L, kind, -1.0, sign_seed=sign, orc=orc)

@@ -329,7 +329,7 @@ typedef struct sdc_sq sdc_sq;
  *                   call's origins), SDC_FLAG_TIMING records HIP events.
  *  device         : HIP device ordinal.
  * Allocates all device memory the accumulator needs: the spins packed in
- * FP64 by chunks of 32 sites (24 bytes per site and frame), the per-site-
+ * FP64 by chunks of 24 sites (24 bytes per site and frame), the per-site-
  * range partial transforms (at most 1 GiB) and the [n_q][3T] transform.
  * Errors: INVALID_ARG, UNSUPPORTED, OOM, NO_DEVICE, HIP.
  */

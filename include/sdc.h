@@ -522,6 +522,13 @@ sdc_status sdc_mc_run(sdc_mc* mc, const sdc_mc_spec* schedule, const float* init
  * INVALID_ARG, STATE, HIP. */
 sdc_status sdc_mc_timings(sdc_mc* mc, double* ms);
 
+/* Which sweep kernel the object uses: *stencil = 1 when the neighbours
+ * follow from lattice arithmetic (periodic sc box with even edges and a
+ * uniform coupling, checked at create to reproduce the bond tables bit for
+ * bit; the sweeps read 52 fewer bytes per update), 0 when they are read from
+ * the bond tables.  Both give the same result.  Errors: INVALID_ARG. */
+sdc_status sdc_mc_uses_stencil(const sdc_mc* mc, int32_t* stencil);
+
 /* Free the object (waits for the device).  NULL is a no-op. */
 sdc_status sdc_mc_destroy(sdc_mc* mc);
 

@@ -355,6 +355,15 @@ struct McArgs {
     double* S;                 // [n slots][3] FP64 state
     double* cone;              // [2]: cone half-angle, its cosine
     unsigned long long* accepted;  // accepted moves of the current sweep (mc_counter_bytes())
+    // Lattice stencil (set only when the host has checked that it reproduces
+    // the tables above slot for slot): periodic sc box L0 x L1 x L2, every edge
+    // even, site (x L1 + y) L2 + z, two colour classes (the checkerboard),
+    // class c in slots c n/2 .. (c + 1) n/2 in site order, bonds +x, -x, +y,
+    // -y, +z, -z with coupling st_j and DMI vectors (st_dp, st_dz, st_dz)
+    // rotated onto each axis, st_dn for the negative directions.
+    int stencil;
+    int L0, L1, L2;
+    float st_j, st_dp, st_dn, st_dz;
 };
 int mc_energy_blocks(int64_t n);
 size_t mc_counter_bytes();

@@ -34,6 +34,11 @@ constexpr int kMcCounterStride = 16;  // u64 words between counters
 // x q + min(x, r) + b / 8 of the class (x = b mod 8, nb = 8 q + r blocks), so
 // each XCD sweeps one contiguous stretch of slots in order and its L2 keeps
 // the neighbour planes that the following slots read again.
+// STENCIL: the site and its neighbours' slots follow from the slot by
+// lattice arithmetic (McArgs::stencil), so the slot -> site map and the bond
+// tables are not read; the sums run over the bonds in table order with the
+// table's values, so both forms give the same bits.
+template <int STENCIL>
 __global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, int64_t k0, int64_t count, double T,
                                                         int64_t sweep) {
     const int64_t nb = gridDim.x, q = nb / 8, r = nb % 8, x = blockIdx.x % 8;
@@ -42,23 +47,51 @@ __global__ __launch_bounds__(256) void mc_colour_kernel(McArgs a, int64_t k0, in
     bool accepted = false;
     if (t < count) {
         const int64_t k = k0 + t;           // slot
-        const int64_t i = a.site_of[k];     // site index: the Philox counter
+        int64_t i;                          // site index: the Philox counter
         // field of the neighbours: sum_j (J_ij S_j + D_ij x S_j)
         double w0 = 0.0, w1 = 0.0, w2 = 0.0;
-        for (int e = 0; e < a.z_max; ++e) {
-            const int32_t j = a.nbr[k * a.z_max + e];
-            if (j < 0) continue;
-            const double J = a.jval[k * a.z_max + e];
-            const double y0 = a.S[3 * (int64_t)j], y1 = a.S[3 * (int64_t)j + 1], y2 = a.S[3 * (int64_t)j + 2];
+        auto bond = [&](int64_t j, double J, double d0, double d1, double d2, bool dmi) {
+            const double y0 = a.S[3 * j], y1 = a.S[3 * j + 1], y2 = a.S[3 * j + 2];
             w0 += J * y0;
             w1 += J * y1;
             w2 += J * y2;
-            if (a.dvec) {
-                const float* d = a.dvec + 3 * (k * a.z_max + e);
-                const double d0 = d[0], d1 = d[1], d2 = d[2];
+            if (dmi) {
                 w0 += d1 * y2 - d2 * y1;
                 w1 += d2 * y0 - d0 * y2;
                 w2 += d0 * y1 - d1 * y0;
+            }
+        };
+        if constexpr (STENCIL) {
+            // class c = (k0 > 0) holds the sites of parity c of x + y + z in
+            // site order; with L2 even its t-th site is 2t or 2t + 1
+            const int64_t half = a.n / 2, s0 = 2 * t;
+            const int64_t row = s0 / a.L2, z0 = s0 - row * a.L2;
+            const int64_t y = row % a.L1, xx = row / a.L1;
+            const int64_t dl = (k0 > 0 ? 1 : 0) ^ ((xx + y) & 1);
+            const int64_t z = z0 + dl;
+            i = s0 + dl;
+            const int64_t other = k0 > 0 ? 0 : half;  // first slot of the neighbours' class
+            const int64_t xp = xx + 1 < a.L0 ? xx + 1 : 0, xm = xx > 0 ? xx - 1 : a.L0 - 1;
+            const int64_t yp = y + 1 < a.L1 ? y + 1 : 0, ym = y > 0 ? y - 1 : a.L1 - 1;
+            const int64_t zp = z + 1 < a.L2 ? z + 1 : 0, zm = z > 0 ? z - 1 : a.L2 - 1;
+            const int64_t rxy = row * a.L2;  // (x L1 + y) L2
+            const int64_t sj[6] = {((xp * a.L1 + y) * a.L2 + z), ((xm * a.L1 + y) * a.L2 + z),
+                                   ((xx * a.L1 + yp) * a.L2 + z), ((xx * a.L1 + ym) * a.L2 + z),
+                                   rxy + zp, rxy + zm};
+            const bool dmi = a.dvec != nullptr;
+            const double J = a.st_j, dp = a.st_dp, dn = a.st_dn, dz = a.st_dz;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const double dd = (e & 1) ? dn : dp;
+                bond(other + (sj[e] >> 1), J, e / 2 == 0 ? dd : dz, e / 2 == 1 ? dd : dz, e / 2 == 2 ? dd : dz, dmi);
+            }
+        } else {
+            i = a.site_of[k];
+            for (int e = 0; e < a.z_max; ++e) {
+                const int32_t j = a.nbr[k * a.z_max + e];
+                if (j < 0) continue;
+                const float* d = a.dvec ? a.dvec + 3 * (k * a.z_max + e) : nullptr;
+                bond(j, a.jval[k * a.z_max + e], d ? d[0] : 0.0, d ? d[1] : 0.0, d ? d[2] : 0.0, d != nullptr);
             }
         }
         double* si = a.S + 3 * k;
@@ -226,7 +259,10 @@ int launch_mc_sweep(const McArgs& a, const int64_t* class_start, int n_classes, 
         const int64_t count = class_start[c + 1] - class_start[c];
         if (count == 0) continue;
         const unsigned grid = (unsigned)((count + 255) / 256);
-        hipLaunchKernelGGL(mc_colour_kernel, dim3(grid), dim3(256), 0, s, a, class_start[c], count, T, sweep);
+        if (a.stencil)
+            hipLaunchKernelGGL(mc_colour_kernel<1>, dim3(grid), dim3(256), 0, s, a, class_start[c], count, T, sweep);
+        else
+            hipLaunchKernelGGL(mc_colour_kernel<0>, dim3(grid), dim3(256), 0, s, a, class_start[c], count, T, sweep);
     }
     hipLaunchKernelGGL(mc_cone_kernel, dim3(1), dim3(64), 0, s, a, history, sweep);
     return (int)hipGetLastError();

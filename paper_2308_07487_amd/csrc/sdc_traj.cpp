@@ -347,6 +347,56 @@ struct sdc_mc {
 
 namespace {
 
+uint32_t float_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, sizeof u);
+    return u;
+}
+
+// The colour kernel's lattice stencil (McArgs::stencil) for a periodic sc box
+// with even edges and one uniform coupling: turned on only when it gives the
+// slot -> site map and every neighbour slot, coupling and DMI vector of the
+// slot-ordered tables bit for bit, so both kernels compute the same sweep.
+void mc_stencil(const sdc_mc_spec* spec, int64_t n, int n_col, const std::vector<int64_t>& start,
+                const std::vector<int32_t>& order, const Bonds& b, sdc::McArgs* ma) {
+    ma->stencil = 0;
+    if (spec->kind != SDC_BINS_PERIODIC_SC || spec->coupling != SDC_COUPLING_NN_UNIFORM || n_col != 2 || b.z != 6 ||
+        n % 2 != 0 || start[1] != n / 2)
+        return;
+    for (int a = 0; a < 3; ++a)
+        if (spec->cells[a] < 2 || spec->cells[a] % 2 != 0) return;
+    const int64_t L0 = spec->cells[0], L1 = spec->cells[1], L2 = spec->cells[2], half = n / 2;
+    const float jf = (float)spec->J;
+    // the DMI table entries D (r_j - r_i) / |r_j - r_i| for steps of +-2 or 0
+    // in doubled coordinates, rounded as the table rounds them
+    const float dp = (float)(spec->D * 2 / 2.0), dn = (float)(spec->D * -2 / 2.0), dz = (float)(spec->D * 0 / 2.0);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t c = k >= half ? 1 : 0, s0 = 2 * (k - c * half);
+        const int64_t row = s0 / L2, z0 = s0 - row * L2, y = row % L1, x = row / L1;
+        const int64_t dl = c ^ ((x + y) & 1), z = z0 + dl;
+        if (order[(size_t)k] != s0 + dl) return;
+        const int64_t other = c ? 0 : half;
+        const int64_t sj[6] = {((((x + 1) % L0) * L1 + y) * L2 + z), ((((x + L0 - 1) % L0) * L1 + y) * L2 + z),
+                               ((x * L1 + (y + 1) % L1) * L2 + z), ((x * L1 + (y + L1 - 1) % L1) * L2 + z),
+                               row * L2 + (z + 1) % L2, row * L2 + (z + L2 - 1) % L2};
+        for (int e = 0; e < 6; ++e) {
+            const size_t be = (size_t)(k * 6 + e);
+            if (b.nbr[be] != other + (sj[e] >> 1) || float_bits(b.jv[be]) != float_bits(jf)) return;
+            if (!b.dv.empty())
+                for (int a = 0; a < 3; ++a)
+                    if (float_bits(b.dv[be * 3 + a]) != float_bits(a == e / 2 ? ((e & 1) ? dn : dp) : dz)) return;
+        }
+    }
+    ma->stencil = 1;
+    ma->L0 = (int)L0;
+    ma->L1 = (int)L1;
+    ma->L2 = (int)L2;
+    ma->st_j = jf;
+    ma->st_dp = dp;
+    ma->st_dn = dn;
+    ma->st_dz = dz;
+}
+
 bool mc_alloc(sdc_mc* m, void** p, size_t bytes) {
     if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
         (void)hipGetLastError();
@@ -476,6 +526,7 @@ extern "C" sdc_status sdc_mc_create(const float* positions_host, int64_t n_sites
         ma.S = d_S;
         ma.cone = d_cone;
         ma.accepted = d_acc;
+        mc_stencil(spec, n_sites, m->n_col, m->start, order, b, &ma);
     } catch (const std::bad_alloc&) {
         delete m;
         return sdc::set_error(SDC_ERR_OOM, "host allocation failed");
@@ -543,6 +594,12 @@ extern "C" sdc_status sdc_mc_timings(sdc_mc* m, double* ms) {
     if (hipEventElapsedTime(&t, m->ev[0], m->ev[1]) != hipSuccess)
         return sdc::set_error(SDC_ERR_HIP, "hipEventElapsedTime");
     *ms = t;
+    return sdc::set_error(SDC_OK, "");
+}
+
+extern "C" sdc_status sdc_mc_uses_stencil(const sdc_mc* m, int32_t* stencil) {
+    if (!m || !stencil) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    *stencil = m->args.stencil;
     return sdc::set_error(SDC_OK, "");
 }
 

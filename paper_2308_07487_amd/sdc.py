@@ -72,7 +72,8 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_batch_create", "sdc_batch_accumulate", "sdc_batch_timings", "sdc_batch_info",
            "sdc_batch_destroy", "sdc_plan_structure_factor", "sdc_sq_create", "sdc_sq_accumulate",
            "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy", "sdc_mc_n_sweeps",
-           "sdc_mc_anneal", "sdc_mc_create", "sdc_mc_run", "sdc_mc_timings", "sdc_mc_destroy")
+           "sdc_mc_anneal", "sdc_mc_create", "sdc_mc_run", "sdc_mc_timings", "sdc_mc_uses_stencil",
+           "sdc_mc_destroy")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -117,6 +118,7 @@ def lib():
         L.sdc_mc_create.argtypes = [P, i64, ctypes.POINTER(McSpec), ctypes.c_int, ctypes.POINTER(P)]
         L.sdc_mc_run.argtypes = [P, ctypes.POINTER(McSpec), P, P, P, P, P]
         L.sdc_mc_timings.argtypes = [P, P]
+        L.sdc_mc_uses_stencil.argtypes = [P, ctypes.POINTER(i32)]
         L.sdc_mc_destroy.argtypes = [P]
         L.sdc_sq_create.argtypes = [P, i64, P, i32, ctypes.POINTER(SqSpec), ctypes.c_int, ctypes.POINTER(P)]
         L.sdc_sq_accumulate.argtypes = [P, P, i64, P]
@@ -460,6 +462,14 @@ class MonteCarlo:
         ms = np.zeros(1)
         _check(lib().sdc_mc_timings(self._h, _np_ptr(ms)), "sdc_mc_timings")
         return float(ms[0])
+
+    @property
+    def uses_stencil(self):
+        """True when the sweeps compute neighbours by lattice arithmetic
+        instead of reading the bond tables (same results)."""
+        v = ctypes.c_int32()
+        _check(lib().sdc_mc_uses_stencil(self._h, ctypes.byref(v)), "sdc_mc_uses_stencil")
+        return bool(v.value)
 
     def close(self):
         if self._h is not None:

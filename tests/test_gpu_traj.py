@@ -229,17 +229,20 @@ def _f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("kind,L", [("sc", (4, 6, 5)), ("bcc", (3, 4, 4)), ("radial", None),
-                                    ("sc", (24, 24, 20))])
-def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind, L):
+@pytest.mark.parametrize("kind,L,D", [("sc", (4, 6, 5), 0.3), ("bcc", (3, 4, 4), 0.3), ("radial", None, 0.3),
+                                      ("sc", (24, 24, 20), 0.3), ("sc", (2, 4, 2), -0.2)])
+def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind, L, D):
     """Annealed Metropolis sweeps with every term of Eq. (1): the GPU's colour
     classes, Philox moves and cone adaptation against the oracle's on the
     same bonds (fp32 tables, as the library builds them).  Accepted moves per
     sweep agree exactly; the states agree to the fp32 output.  The 24x24x20
     box has 5760 sites per colour class: 23 workgroups per class, spread over
-    the XCDs in unequal stretches (3 for seven of them, 2 for the last)."""
-    _say(f"mc anneal {kind} {L}")
-    D, A, Hz, seed = 0.3, 0.2, 0.4, 0x5DC0A101
+    the XCDs in unequal stretches (3 for seven of them, 2 for the last); it
+    and the 2x4x2 box (both x and z neighbours of a site coincide; D < 0, so
+    the DMI table's zero components are -0) run the lattice-stencil sweeps,
+    the others the table sweeps."""
+    _say(f"mc anneal {kind} {L} D={D}")
+    A, Hz, seed = 0.2, 0.4, 0x5DC0A101
     if kind == "radial":
         pos = inputs.ball_positions(300, 3.0, seed=9)
         row, col, Jv = _cutoff_csr(pos, 1.0, 1.5)
@@ -272,6 +275,24 @@ def test_mc_anneal_matches_oracle(torch_dev, S, orc, kind, L):
     assert np.abs(got - ref[0]).max() < 2e-7
     assert abs(E - ref[2]) < 1e-10 * max(1.0, abs(ref[2])) and abs(cone - ref[3]) < 1e-12
     assert 0 < acc.sum() < acc.shape[0] * n  # some moves accepted, some rejected
+
+
+def test_mc_stencil_selection(torch_dev, S):
+    """The lattice-stencil sweeps are taken for periodic sc boxes with even
+    edges and one uniform coupling, and only there."""
+    _say("mc stencil selection")
+    for L, coupling, D, expect in [((24, 24, 20), S.COUPLING_NN_UNIFORM, 0.3, True),
+                                   ((2, 4, 2), S.COUPLING_NN_UNIFORM, -0.2, True),
+                                   ((128, 128, 128), S.COUPLING_NN_UNIFORM, 0.0, True),
+                                   ((4, 6, 5), S.COUPLING_NN_UNIFORM, 0.0, False),
+                                   ((6, 6, 6), S.COUPLING_NN_RANDOM_SIGN, 0.0, False),
+                                   ((32, 32, 1), S.COUPLING_NN_UNIFORM, 0.0, False)]:
+        spec = S.mc_spec(S.BINS_SC, cells=L, coupling=coupling, J=-1.0, D=D)
+        with S.MonteCarlo(inputs.sc_positions(L), spec) as mc:
+            assert mc.uses_stencil == expect, (L, coupling, D)
+    spec = S.mc_spec(S.BINS_BCC, cells=(4, 4, 4), J=-1.0)
+    with S.MonteCarlo(inputs.bcc_positions((4, 4, 4)), spec) as mc:
+        assert not mc.uses_stencil
 
 
 def test_mc_independent_spins_equilibrium(torch_dev, S):

@@ -38,7 +38,7 @@ typedef enum {
     SDC_ERR_STATE = 2,        /* call not allowed in the plan's current state */
     SDC_ERR_OOM = 3,          /* host or device allocation failed             */
     SDC_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed   */
-    SDC_ERR_UNSUPPORTED = 5,  /* valid request outside what this build does   */
+    SDC_ERR_UNSUPPORTED = 5,  /* valid request outside what the library does */
     SDC_ERR_NO_DEVICE = 6     /* no usable gfx950 device                      */
 } sdc_status;
 

@@ -4,7 +4,9 @@ even numbers of 8-origin blocks (both K-step addressings of the fused
 kernel), origin strides, lag counts that leave partial lag groups, lag
 subsets, every precision and the connected form, for sc, bcc and radial
 bins.  Each case: pair counts bit-exact, origin totals exact, C(r, t) within
-the precision's bar against the FP64 oracle."""
+the precision's bar against the FP64 oracle.  A second sweep does the same
+for the q-resolved S(q, t) accumulator (site, wave-vector and frame counts
+that leave ragged chunks, blocks and column groups; connected form)."""
 import numpy as np
 import pytest
 
@@ -93,3 +95,44 @@ def test_random_configuration(torch_dev, S, orc, case):
     assert e <= bar
     untouched = np.setdiff1d(np.arange(n_L), lags)
     np.testing.assert_array_equal(out["C"][untouched], 0.0)
+
+
+def _sq_cases(n=12, seed=0x5DC05EEE):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        n_sites = int(rng.integers(1, 300))
+        n_q = int(rng.integers(1, 72))
+        n_o = int(rng.integers(1, 12))
+        n_L = int(rng.integers(1, 64))
+        stride = int(rng.integers(1, 4))
+        connected = bool(rng.random() < 0.4)
+        out.append((k, n_sites, n_q, n_o, n_L, stride, connected))
+    return out
+
+
+SQ_CASES = _sq_cases()
+
+
+@pytest.mark.parametrize("case", SQ_CASES,
+                         ids=[f"{c[0]}-n{c[1]}-q{c[2]}-o{c[3]}-l{c[4]}-s{c[5]}{'-conn' if c[6] else ''}" for c in SQ_CASES])
+def test_random_q_resolved(torch_dev, S, orc, case):
+    """S(q, t) of Eq. (3) at arbitrary wave vectors (q = 0 among them) on
+    random point sets: site counts that leave ragged 24-site chunks, wave
+    vector counts that leave partial 64- and 16-row blocks, frame counts that
+    leave partial 64-frame column groups; FP64 against the oracle's pair sum
+    within 1e-9 normwise."""
+    k, n, n_q, n_o, n_L, s, connected = case
+    print(f"[case] q-resolved sweep {case}", flush=True)
+    pos = inputs.ball_positions(n, 5.0, seed=400 + k)
+    fr = inputs.random_unit_frames((n_o - 1) * s + n_L + (k % 2), n, seed=500 + k)
+    rng = np.random.default_rng(600 + k)
+    q = rng.uniform(-2.0, 2.0, size=(n_q, 3))
+    q[0] = 0.0
+    with S.StructureFactor(pos, q, n_o, n_L, origin_stride=s, connected=connected) as sq:
+        sq.accumulate(torch_dev.from_numpy(fr).to("cuda"))
+        sqt, _ = sq.finalize()
+    ref = orc.structure_factor_q(pos, fr, n_o, list(range(n_L)), q, stride=s, connected=connected)
+    e = float(np.max(np.abs(sqt - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    print(f"  normwise error {e:.2e}", flush=True)
+    assert e <= 1e-9

@@ -6,7 +6,8 @@ subsets, every precision and the connected form, for sc, bcc and radial
 bins.  Each case: pair counts bit-exact, origin totals exact, C(r, t) within
 the precision's bar against the FP64 oracle.  A second sweep does the same
 for the q-resolved S(q, t) accumulator (site, wave-vector and frame counts
-that leave ragged chunks, blocks and column groups; connected form)."""
+that leave ragged chunks, blocks and column groups; connected form), a third
+for random sets of plans in one persistent batch launch."""
 import numpy as np
 import pytest
 
@@ -136,3 +137,67 @@ def test_random_q_resolved(torch_dev, S, orc, case):
     e = float(np.max(np.abs(sqt - ref)) / max(np.max(np.abs(ref)), 1e-300))
     print(f"  normwise error {e:.2e}", flush=True)
     assert e <= 1e-9
+
+
+def _batch_cases(n=6, seed=0x5DC05EEF):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        radial = k % 3 == 2
+        prec = PRECS[int(rng.integers(0, 4))]
+        plans = []
+        for m in range(int(rng.integers(2, 7))):
+            if radial:
+                geo = ("radial", (int(rng.integers(10, 250)), int(rng.integers(5, 150))))
+            else:
+                lat = "sc" if rng.random() < 0.5 else "bcc"
+                hi = 8 if lat == "sc" else 5
+                geo = (lat, tuple(int(x) for x in rng.integers(1, hi, size=3)))
+            plans.append(geo + (int(rng.integers(1, 41)), int(rng.integers(1, 41)), int(rng.integers(1, 3)),
+                                bool(rng.random() < 0.3)))
+        out.append((k, prec, plans))
+    return out
+
+
+BATCH_CASES = _batch_cases()
+
+
+@pytest.mark.parametrize("case", BATCH_CASES, ids=[f"{c[0]}-{c[1]}-{len(c[2])}plans" for c in BATCH_CASES])
+def test_random_batch(torch_dev, S, orc, case):
+    """Random sets of plans (periodic sc/bcc mixed, or radial; different
+    sizes, origin counts, lags, strides, connected flags) accumulated in one
+    persistent launch: every plan's counts, origin totals and raw bins against
+    the oracle, within the precision's bar."""
+    k, prec, specs = case
+    print(f"[case] batch sweep {k} {prec}: {specs}", flush=True)
+    plans, frames, host = [], [], []
+    try:
+        for m, (lat, geo, n_o, n_L, s, connected) in enumerate(specs):
+            if lat == "sc":
+                pos, gk, ok, kw = inputs.sc_positions(geo), S.BINS_SC, orc.SC, dict(cells=geo)
+            elif lat == "bcc":
+                pos, gk, ok, kw = inputs.bcc_positions(geo), S.BINS_BCC, orc.BCC, dict(cells=geo)
+            else:
+                pos = inputs.ball_positions(geo[0], 3.0, seed=700 + 10 * k + m)
+                gk, ok, kw = S.BINS_RADIAL, orc.RADIAL, dict(n_shells=geo[1], r_max=6.0)
+            fr = inputs.random_unit_frames((n_o - 1) * s + n_L, pos.shape[0], seed=800 + 10 * k + m)
+            plans.append(S.Plan(pos, gk, n_o, n_L, prec, origin_stride=s, connected=connected, **kw))
+            frames.append(torch_dev.from_numpy(fr).cuda())
+            host.append((pos, ok, kw, fr, n_o, n_L, s, connected))
+        with S.Batch(plans) as b:
+            b.accumulate(frames)
+            torch_dev.cuda.synchronize()
+        bar = 5e-5 if prec == "split_bf16" else 1e-6
+        for p, (pos, ok, kw, fr, n_o, n_L, s, connected) in zip(plans, host):
+            out = p.finalize()
+            H, no, sf, ms = p.raw()
+            Hr, cr = orc.binned_corr(pos, fr, ok, n_o, np.arange(n_L), stride=s, connected=connected, **kw)
+            np.testing.assert_array_equal(out["counts"], cr)
+            np.testing.assert_array_equal(no, float(n_o))
+            e = float(np.max(np.abs(H - Hr))) / max(float(np.max(np.abs(Hr))), 1e-300)
+            print(f"  N={pos.shape[0]} n_o={n_o} n_L={n_L} s={s}{' conn' if connected else ''}: "
+                  f"raw-bin error {e:.3e}", flush=True)
+            assert e <= bar
+    finally:
+        for p in plans:
+            p.close()

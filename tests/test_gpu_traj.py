@@ -352,3 +352,71 @@ def test_mc_object_runs(torch_dev, S):
         three = torch_dev.zeros_like(init)
         _, info3 = mc.run(spec, three, info=True)  # continues from the FP64 state
         assert info3[0] < E1 and mc.timings() > 0.0
+
+
+def _mc_cases(n=10, seed=0x5DC05EF0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        kind = ("sc", "sc", "bcc", "radial", "bcc")[k % 5]
+        if kind == "sc":
+            # all edges even: the lattice-stencil sweeps; otherwise the table sweeps
+            even = rng.random() < 0.5
+            L = tuple(int(2 * rng.integers(1, 5)) if even else int(rng.integers(2, 9)) for _ in range(3))
+        elif kind == "bcc":
+            L = tuple(int(x) for x in rng.integers(2, 5, size=3))
+        else:
+            L = int(rng.integers(30, 300))
+        sign = kind == "bcc" and rng.random() < 0.5
+        J = float(rng.choice([-1.0, 1.0]))
+        D = float(rng.uniform(-0.4, 0.4)) if rng.random() < 0.6 else 0.0
+        A, Hz = float(rng.uniform(-0.3, 0.3)), float(rng.uniform(-0.5, 0.5))
+        T0 = float(rng.uniform(0.5, 3.0))
+        sched = (T0, T0 * float(rng.uniform(0.1, 0.9)), float(rng.uniform(0.5, 0.9)), int(rng.integers(1, 4)),
+                 int(rng.integers(0, 6)), float(rng.uniform(0.2, np.pi)), float(rng.uniform(0.1, 0.5)))
+        out.append((k, kind, L, sign, J, D, A, Hz, sched))
+    return out
+
+
+MC_CASES = _mc_cases()
+
+
+@pytest.mark.parametrize("case", MC_CASES, ids=[f"{c[0]}-{c[1]}-{c[2]}" for c in MC_CASES])
+def test_mc_random_matches_oracle(torch_dev, S, orc, case):
+    """Seeded random models and schedules (sc boxes with even edges on the
+    stencil sweeps and others on the table sweeps, bcc with uniform or
+    random-sign bonds, radial cutoff couplings; random J sign, DMI,
+    anisotropy, field, temperatures, cooling, sweep counts, initial cone and
+    acceptance target): accepted moves per sweep exactly the oracle's."""
+    k, kind, L, sign, J, D, A, Hz, (T0, T1, cool, spt, sf, cone0, target) = case
+    _say(f"mc random {case}")
+    seed = 0x5DC0A200 + k
+    if kind == "radial":
+        pos = inputs.ball_positions(L, 3.0, seed=900 + k)
+        row, col, Jv = _cutoff_csr(pos, J, 1.5)
+        rij = pos[col].astype(np.float64) - pos[np.repeat(np.arange(pos.shape[0]), np.diff(row))].astype(np.float64)
+        Dv = D * rij / np.linalg.norm(rij, axis=1, keepdims=True)
+        spec = S.mc_spec(S.BINS_RADIAL, coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5, J=J)
+    else:
+        pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+        row, col, Jv = _nn_csr(pos, L, kind, J, sign_seed=seed if sign else None, orc=orc)
+        Dv = _dmi_lattice(pos.shape[0], kind, D)
+        spec = S.mc_spec(S.BINS_SC if kind == "sc" else S.BINS_BCC, cells=L,
+                         coupling=S.COUPLING_NN_RANDOM_SIGN if sign else S.COUPLING_NN_UNIFORM, J=J)
+    spec.D, spec.A, spec.Hz, spec.seed = D, A, Hz, seed
+    spec.T_start, spec.T_end, spec.cool, spec.sweeps_per_T, spec.sweeps_final = T0, T1, cool, spt, sf
+    spec.cone0, spec.acc_target = cone0, target
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=1000 + k)[0]
+    st = torch_dev.from_numpy(init).cuda()
+    out = torch_dev.zeros_like(st)
+    acc, E, cone, T, ncol = S.mc_anneal(pos, spec, st, out)
+    ref = orc.mc_anneal(row, col, _f32(Jv), init, seed, T0, T1, cool, spt, sf, cone0=cone0, acc_target=target,
+                        D=_f32(Dv) if D != 0.0 else None, A=A, Hz=Hz)
+    got = out.cpu().numpy()
+    print(f"  {n} sites, {acc.shape[0]} sweeps, colours {ncol}, accepted {acc.sum()}/{ref[1].sum()}, "
+          f"state diff {np.abs(got - ref[0]).max():.2e}", flush=True)
+    assert ncol == ref[5] and T == ref[4]
+    np.testing.assert_array_equal(acc, ref[1])
+    assert np.abs(got - ref[0]).max() < 2e-7
+    assert abs(E - ref[2]) < 1e-10 * max(1.0, abs(ref[2])) and abs(cone - ref[3]) < 1e-12

@@ -420,3 +420,57 @@ def test_mc_random_matches_oracle(torch_dev, S, orc, case):
     np.testing.assert_array_equal(acc, ref[1])
     assert np.abs(got - ref[0]).max() < 2e-7
     assert abs(E - ref[2]) < 1e-10 * max(1.0, abs(ref[2])) and abs(cone - ref[3]) < 1e-12
+
+
+def _rk4_cases(n=8, seed=0x5DC05EF1):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        kind = ("sc", "bcc", "radial", "sc")[k % 4]
+        if kind == "radial":
+            L = int(rng.integers(20, 300))
+        else:
+            L = tuple(int(x) for x in rng.integers(2, 7 if kind == "sc" else 5, size=3))
+        sign = kind == "bcc" and rng.random() < 0.5
+        J = float(rng.choice([-1.0, 1.0]) * rng.uniform(0.5, 1.5))
+        D = float(rng.uniform(-0.4, 0.4)) if rng.random() < 0.6 else 0.0
+        A = float(rng.uniform(-0.3, 0.3)) if rng.random() < 0.6 else 0.0
+        Hz = float(rng.uniform(-0.6, 0.6)) if rng.random() < 0.6 else 0.0
+        dt = float(rng.choice([0.002, 0.005, 0.01]))
+        nf = int(rng.integers(2, 30))
+        out.append((k, kind, L, sign, J, D, A, Hz, dt, nf))
+    return out
+
+
+RK4_CASES = _rk4_cases()
+
+
+@pytest.mark.parametrize("case", RK4_CASES, ids=[f"{c[0]}-{c[1]}-{c[2]}" for c in RK4_CASES])
+def test_rk4_random_matches_oracle(torch_dev, S, orc, case):
+    """Seeded random models (sc, bcc with uniform or random-sign bonds,
+    radial cutoff couplings; random J, DMI, anisotropy, field, step and
+    frame count): the GPU's FP32 RK4 frames against the oracle's FP64 ones."""
+    k, kind, L, sign, J, D, A, Hz, dt, nf = case
+    _say(f"rk4 random {case}")
+    seed = 0x5DC0A300 + k
+    if kind == "radial":
+        pos = inputs.ball_positions(L, 3.0, seed=1100 + k)
+        row, col, Jv = _cutoff_csr(pos, J, 1.5)
+        rij = pos[col].astype(np.float64) - pos[np.repeat(np.arange(pos.shape[0]), np.diff(row))].astype(np.float64)
+        Dv = D * rij / np.linalg.norm(rij, axis=1, keepdims=True)
+        kw, bins, cells = dict(coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5), S.BINS_RADIAL, (0, 0, 0)
+    else:
+        pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+        row, col, Jv = _nn_csr(pos, L, kind, J, sign_seed=seed if sign else None, orc=orc)
+        Dv = _dmi_lattice(pos.shape[0], kind, D)
+        kw = dict(coupling=S.COUPLING_NN_RANDOM_SIGN if sign else S.COUPLING_NN_UNIFORM, seed=seed if sign else 0)
+        bins, cells = (S.BINS_SC if kind == "sc" else S.BINS_BCC), L
+    n = pos.shape[0]
+    init = inputs.random_unit_frames(1, n, seed=1200 + k)[0]
+    fr = torch_dev.zeros((nf, n, 3), device="cuda")
+    S.traj_generate(pos, bins, fr, cells=cells, J=J, dt=dt, D=D, A=A, Hz=Hz, init=S.INIT_GIVEN,
+                    init_state=torch_dev.from_numpy(init).cuda(), **kw)
+    ref = orc.ll_rk4(row, col, _f32(Jv), init, dt, nf, D=_f32(Dv) if D != 0.0 else None, A=A, Hz=Hz)
+    err = np.abs(fr.cpu().numpy() - ref).max()
+    print(f"  {n} sites, {nf} frames: max error {err:.2e}", flush=True)
+    assert err < 5e-6

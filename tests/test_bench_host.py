@@ -39,3 +39,10 @@ def test_traffic_lookup_checks_the_sources(tmp_path, monkeypatch):
 def test_workloads_are_defined():
     for name in ("sc36_afm", "sc32_fm", "ball65k", "batch48", "sq420", "ball65k_sq", "mc_sc128"):
         assert name in bench.WORKLOADS
+
+
+def test_unknown_compare_precision_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--compare", "''"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "--compare" in r.stderr

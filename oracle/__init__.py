@@ -18,6 +18,11 @@ Each function states the paper passage it follows (arXiv 2308.07487):
                        at any wave vector (``structure_factor``: the ones
                        commensurate with a periodic box); ``connected`` takes
                        Eq. (4) with its second term.
+- ``binned_corr_fft``  the same H on periodic lattices through the
+                       correlation theorem (numpy FFT): a special case that
+                       reduces to a library routine, pinned against
+                       ``binned_corr``, for checks of every bin and lag at the
+                       workloads' full sizes.
 - ``finalize``         per-bin normalisation, site sum (Sec. 1: summing the
                        correlation over all sites) and the windowed time
                        transform of Sec. 2.2.
@@ -163,6 +168,86 @@ def binned_corr(pos, frames, kind, n_origins, lags, stride=1, cells=None, n_shel
         H -= mean_product(pos, frames, kind, n_origins, lags, stride=stride, cells=cells,
                           n_shells=n_shells, r_max=r_max, rows=rows, n_threads=n_threads)
     return H, C
+
+
+def _fast_len(n):
+    """Smallest 2^a 3^b 5^c >= n (an FFT length numpy handles quickly)."""
+    m = n
+    while True:
+        r = m
+        for f in (2, 3, 5):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            return m
+        m += 1
+
+
+def binned_corr_fft(pos, frames, kind, n_origins, lags, cells, stride=1):
+    """H[l][b] of ``binned_corr`` for the periodic kinds through the
+    correlation theorem (numpy FFT, FP64), for checks of every bin and lag at
+    sizes the double loop cannot reach.
+
+    On a periodic lattice the bin of a pair is the displacement class, so
+    H(d, t) = sum_o sum_x sum_alpha S_alpha(o s, x) S_alpha(o s + t, x + d),
+    a cross-correlation over the periodic site grid and, with the origin
+    frames o s kept and every other frame zeroed on the origin side, over
+    time as well: one 4D correlation per component, conj(F[A]) F[B] in
+    Fourier space (A real).  The time axis is zero-padded past
+    (n_origins - 1) s + max lag, so no lag wraps around.  bcc is two
+    interleaved sc grids: parity-0 bins take the same-sublattice
+    correlations, parity-1 bins the corner-to-centre one plus the
+    centre-to-corner one shifted by a cell (its key subtracts (1,1,1)).
+    Pinned against ``binned_corr`` (tests/test_oracle.py)."""
+    if kind not in (SC, BCC):
+        raise ValueError("binned_corr_fft needs a periodic kind")
+    L = tuple(int(c) for c in cells)
+    p = np.asarray(pos, dtype=np.float64)
+    f = np.asarray(frames)
+    n = p.shape[0]
+    if kind == SC:
+        cell = np.rint(p).astype(np.int64) % np.array(L)
+        beta = np.zeros(n, dtype=np.int64)
+    else:
+        d = np.rint(2.0 * p).astype(np.int64)
+        beta = d[:, 0] % 2
+        cell = ((d - beta[:, None]) // 2) % np.array(L)
+    flat = (cell[:, 0] * L[1] + cell[:, 1]) * L[2] + cell[:, 2]
+    lags = np.asarray(lags, dtype=np.int64)
+    need = (n_origins - 1) * stride + int(lags.max()) + 1
+    if need > f.shape[0]:
+        raise ValueError("not enough frames for the origins and lags")
+    P = _fast_len(need)
+    ncell = L[0] * L[1] * L[2]
+    orig = np.arange(n_origins) * stride
+    nsub = 1 if kind == SC else 2
+    shape = (P,) + L
+    X = {}
+    for a in range(3):
+        FA, FB = [], []
+        for b in range(nsub):
+            sites = np.nonzero(beta == b)[0]
+            G = np.zeros((P, ncell))
+            G[orig[:, None], flat[sites][None, :]] = f[orig][:, sites, a]
+            FA.append(np.fft.rfftn(G.reshape(shape), axes=(0, 1, 2, 3)))
+            G = np.zeros((P, ncell))
+            G[:need, flat[sites]] = f[:need][:, sites, a]
+            FB.append(np.fft.rfftn(G.reshape(shape), axes=(0, 1, 2, 3)))
+            del G
+        for (u, v) in ([(0, 0)] if nsub == 1 else [(0, 0), (1, 1), (0, 1), (1, 0)]):
+            key = (0, 0) if u == v else (u, v)
+            term = np.conj(FA[u]) * FB[v]
+            X[key] = X[key] + term if key in X else term
+    axes = (0, 1, 2, 3)
+    h0 = np.fft.irfftn(X[(0, 0)], s=shape, axes=axes)[lags].reshape(len(lags), ncell)
+    if nsub == 1:
+        return h0
+    h1 = np.fft.irfftn(X[(0, 1)], s=shape, axes=axes)[lags]
+    h1 += np.roll(np.fft.irfftn(X[(1, 0)], s=shape, axes=axes)[lags], shift=(-1, -1, -1), axis=(1, 2, 3))
+    H = np.empty((len(lags), 2 * ncell))
+    H[:, 0::2] = h0
+    H[:, 1::2] = h1.reshape(len(lags), ncell)
+    return H
 
 
 def mean_product(pos, frames, kind, n_origins, lags, stride=1, cells=None, n_shells=0,

@@ -280,6 +280,39 @@ def test_fft_cross_correlation_bcc(orc):
     np.testing.assert_allclose(H[0][1::2], h1.reshape(-1), atol=1e-11)
 
 
+@pytest.mark.parametrize("kind,L,n_o,stride,lags,seed", [
+    ("sc", (6, 5, 4), 3, 1, [0, 2, 5], 31),
+    ("sc", (5, 1, 3), 4, 3, [0, 1, 4, 7], 32),
+    ("sc", (1, 1, 7), 2, 2, [3], 33),
+    ("bcc", (4, 3, 4), 3, 2, [0, 1, 3], 34),
+    ("bcc", (3, 3, 3), 5, 1, [2, 0], 35),
+    ("bcc", (2, 1, 3), 2, 1, [0, 1, 2], 36),
+])
+def test_fft_reference_matches_double_loop(orc, kind, L, n_o, stride, lags, seed):
+    """binned_corr_fft (the correlation theorem through numpy's FFT, the
+    full-size reference of the GPU tests) equals the double loop on every bin
+    and lag, for sc and bcc boxes with one-cell axes, origin strides, lag
+    subsets in any order and shuffled site order."""
+    pos = inputs.sc_positions(L) if kind == "sc" else inputs.bcc_positions(L)
+    ok = orc.SC if kind == "sc" else orc.BCC
+    n = pos.shape[0]
+    T = (n_o - 1) * stride + max(lags) + 3
+    fr = inputs.random_unit_frames(T, n, seed=seed)
+    perm = np.random.default_rng(seed).permutation(n)
+    H, _ = orc.binned_corr(pos[perm], fr[:, perm], ok, n_o, lags, stride=stride, cells=L)
+    Hf = orc.binned_corr_fft(pos[perm], fr[:, perm], ok, n_o, lags, L, stride=stride)
+    np.testing.assert_allclose(Hf, H, rtol=0, atol=1e-12 * np.abs(H).max())
+
+
+def test_fft_reference_rejects_radial_and_short_frames(orc):
+    pos = inputs.sc_positions((3, 3, 3))
+    fr = inputs.random_unit_frames(4, 27, seed=1)
+    with pytest.raises(ValueError):
+        orc.binned_corr_fft(pos, fr, orc.RADIAL, 2, [0], (3, 3, 3))
+    with pytest.raises(ValueError):
+        orc.binned_corr_fft(pos, fr, orc.SC, 3, [2], (3, 3, 3))
+
+
 def test_structure_factor_link_eq3(orc):
     """Eq. (3) link: the direct double sum over sites of exp(-i q.(r_j - r_i))
     S_i(t_o).S_j(t_o+t) equals the binned sum weighted by exp(-i q.d_b)."""

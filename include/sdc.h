@@ -131,6 +131,33 @@ typedef struct {
  * refreshed by sdc_finalize, sdc_plan_raw and sdc_plan_structure_factor. */
 #define SDC_FLAG_DETERMINISTIC 8
 
+/* Schedules of the fused product (Sec. 3.3-3.4: how the per-lag product
+ * and its epilogue are laid out on the matrix cores).  Every schedule forms
+ * the same products in the same precision; results differ only by the order
+ * of the FP32/FP64 roundings.  In every schedule the small products of the
+ * reduced-precision forms (hi*lo, lo*hi; for BF16X3 all but hi*hi) are never
+ * added to a sum that already holds the large ones: there their lowest bits
+ * would be dropped by the matrix cores' alignment, always downwards, a bias
+ * of a fraction of the last place per element and K-step. */
+typedef enum {
+    SDC_SCHED_DEFAULT = 0,  /* tuning entry for the plan's size class, else the library default */
+    SDC_SCHED_ONE_PASS = 1, /* one K loop per tile pair, second accumulator set for the small
+                               products; one workgroup per compute unit.  Every precision. */
+    SDC_SCHED_TWO_PASS = 2  /* SPLIT_BF16 / SPLIT_FP16 only: per tile pair a K loop over
+                               hi*lo + lo*hi, then one adding hi*hi to those sums, in one
+                               accumulator set; two workgroups per compute unit. */
+} sdc_schedule;
+
+/* Tuning of a plan: what the autotuner (sdc_autotune) chooses per size
+ * class.  Zero fields mean "default". */
+typedef struct {
+    int32_t schedule;      /* sdc_schedule                                     */
+    int32_t segment_pairs; /* tile pairs per fused task (pairs that share one  */
+                           /* LDS histogram; one merge into the global bins    */
+                           /* per task): 0 = default (periodic kinds 96,       */
+                           /* radial all pairs of an i-tile), else [1, 2^20]   */
+} sdc_tuning;
+
 typedef struct sdc_plan sdc_plan;
 
 /*
@@ -149,6 +176,57 @@ typedef struct sdc_plan sdc_plan;
 sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites,
                            const sdc_bin_spec* bins, const sdc_corr_spec* corr,
                            int device, sdc_plan** out);
+
+/*
+ * sdc_plan_create with an explicit tuning.  tuning == NULL, or zero fields,
+ * take the entry for the plan's size class from the tuning file named by the
+ * environment variable SDC_TUNING_FILE (written by sdc_autotune; key: device
+ * architecture, bin kind, floor(2 log2 n_sites), K-steps ceil(3 ceil(n_origins
+ * / 8) / 2), precision), else the library defaults (TWO_PASS for the hi/lo
+ * splits, ONE_PASS otherwise; default segments).  sdc_plan_create(...) is
+ * sdc_plan_create_tuned(..., NULL, ...).  A missing or unreadable tuning file
+ * counts as empty.
+ * Errors: as sdc_plan_create; INVALID_ARG for an unknown schedule or a
+ * segment length out of range, UNSUPPORTED for a schedule the precision does
+ * not have.
+ */
+sdc_status sdc_plan_create_tuned(const float* positions_host, int64_t n_sites,
+                                 const sdc_bin_spec* bins, const sdc_corr_spec* corr,
+                                 const sdc_tuning* tuning, int device, sdc_plan** out);
+
+/* The tuning a plan runs with (fields resolved, never 0).
+ * Errors: INVALID_ARG. */
+sdc_status sdc_plan_get_tuning(const sdc_plan* plan, sdc_tuning* tuning);
+
+/*
+ * Autotuner: for one sample shape, times every candidate tuning (each
+ * schedule the precision has x segment lengths {24, 48, 96, 192, 384} for
+ * periodic kinds, {64, 256, all} for radial) on the device and returns the
+ * fastest.  Each candidate gets its own plan and runs one warm-up and three
+ * timed accumulates (HIP events around the fused launch) over the first
+ * min(n_lags, max_lags) lags (max_lags <= 0: all lags) on seeded uniform
+ * unit spins; the per-task work does not depend on the lag count, so a lag
+ * subset ranks the candidates as the whole set does.  The winner is the
+ * smallest median.
+ *  cache_path : JSON tuning file; when not NULL the winner is written under
+ *               the plan's size-class key (other entries are kept; the file
+ *               is replaced atomically), for sdc_plan_create to pick up via
+ *               SDC_TUNING_FILE.
+ *  best       : receives the winner.   best_ms : its median fused time
+ *               (milliseconds), or NULL.
+ * Synchronous; allocates and frees its own plans and spins.
+ * Errors: as sdc_plan_create; HIP; INVALID_ARG if the file cannot be written.
+ */
+sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
+                        const sdc_corr_spec* corr, int device, int32_t max_lags,
+                        const char* cache_path, sdc_tuning* best, double* best_ms);
+
+/* The tuning-file entry for a sample shape: *found = 1 and *tuning set if
+ * cache_path holds one, else *found = 0.  Host only, except that the device's
+ * architecture name is part of the key.  Errors: INVALID_ARG, NO_DEVICE. */
+sdc_status sdc_tuning_lookup(const char* cache_path, int64_t n_sites, const sdc_bin_spec* bins,
+                             const sdc_corr_spec* corr, int device, sdc_tuning* tuning,
+                             int32_t* found);
 
 /* Number of bins of the plan.  Errors: INVALID_ARG. */
 sdc_status sdc_plan_n_bins(const sdc_plan* plan, int64_t* n_bins);
@@ -285,9 +363,23 @@ sdc_status sdc_batch_accumulate(sdc_batch* batch, const float* const* spins_dev,
  * Errors: INVALID_ARG, STATE (flag not set or no accumulate yet), HIP. */
 sdc_status sdc_batch_timings(sdc_batch* batch, double* ms);
 
+/* sdc_batch_create with the schedule of its one launch given: tuning->schedule
+ * (segment_pairs is ignored: each plan keeps its own layout).  tuning == NULL
+ * or SDC_SCHED_DEFAULT takes the schedule that the plans' own tunings give
+ * the most work (sum of n_sites^2 * n_lags * n_origins).  The launch's task
+ * list takes the plans in order of decreasing task length (K-steps times tile
+ * pairs per task).  Errors: as sdc_batch_create; INVALID_ARG for an unknown
+ * schedule, UNSUPPORTED for one the precision does not have. */
+sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32_t flags,
+                                  const sdc_tuning* tuning, sdc_batch** out);
+
 /* Total fused tasks of the batch and the persistent grid (workgroups).
  * Either output may be NULL.  Errors: INVALID_ARG. */
 sdc_status sdc_batch_info(const sdc_batch* batch, int64_t* n_tasks, int32_t* grid);
+
+/* Schedule (sdc_schedule, never DEFAULT) of the batch's launch.
+ * Errors: INVALID_ARG. */
+sdc_status sdc_batch_schedule(const sdc_batch* batch, int32_t* schedule);
 
 /* Free the batch (waits for the device); its plans stay valid.  NULL is a
  * no-op. */

@@ -132,6 +132,7 @@ struct sdc_plan {
     void* d_B = nullptr;
     size_t bytes_A = 0, bytes_B = 0;
     std::map<std::vector<int>, LagSel> sels;
+    sdc_tuning tuning{};  // resolved: schedule (SDC_SCHED_ONE_PASS / TWO_PASS) and segment length
     bool failed = false;
     int batch_refs = 0;  // batches that hold this plan
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -244,6 +245,7 @@ sdc_status fused_args(const sdc_plan* p, const LagSel& sel, sdc::FusedArgs* a) {
     a->n_bins = L.n_bins;
     a->stride = p->corr.origin_stride;
     a->precision = p->corr.precision;
+    a->sched = sdc::sched_index(p->tuning.schedule);
     if ((int64_t)a->n_groups * a->n_streams > (int64_t)INT32_MAX / 2)
         return set_err(SDC_ERR_UNSUPPORTED, "too many fused tasks");
     return SDC_OK;
@@ -333,6 +335,7 @@ struct sdc_batch {
     std::vector<void*> owned;
     sdc::BatchLaunch bl{};
     int flags = 0;
+    int schedule = SDC_SCHED_ONE_PASS;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     bool timed = false;
     ~sdc_batch() {
@@ -369,7 +372,7 @@ sdc_status sdc_layout_keys(const float* positions_host, int64_t n_sites, const s
     std::string err;
     sdc_status s;
     try {
-        s = sdc::build_layout(positions_host, n_sites, bins, &lay, &err);
+        s = sdc::build_layout(positions_host, n_sites, bins, sdc::default_segment_pairs(bins->kind), &lay, &err);
     } catch (const std::bad_alloc&) {
         return set_err(SDC_ERR_OOM, "host allocation failed");
     }
@@ -418,19 +421,28 @@ sdc_status sdc_layout_keys(const float* positions_host, int64_t n_sites, const s
 
 sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
                            const sdc_corr_spec* corr, int device, sdc_plan** out) {
+    return sdc_plan_create_tuned(positions_host, n_sites, bins, corr, nullptr, device, out);
+}
+
+sdc_status sdc_plan_create_tuned(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
+                                 const sdc_corr_spec* corr, const sdc_tuning* tuning, int device, sdc_plan** out) {
     g_err.clear();
     if (!out) return set_err(SDC_ERR_INVALID_ARG, "null output pointer");
     *out = nullptr;
     if (!positions_host) return set_err(SDC_ERR_INVALID_ARG, "null positions");
     sdc_status s = check_specs(bins, corr);
     if (s != SDC_OK) return s;
+    sdc_tuning tu{};
+    s = sdc::resolve_tuning(tuning, n_sites, bins, corr, device, &tu);
+    if (s != SDC_OK) return s;
     sdc_plan* p = nullptr;
     try {
         p = new sdc_plan();
         p->bins = *bins;
         p->corr = *corr;
+        p->tuning = tu;
         std::string err;
-        s = sdc::build_layout(positions_host, n_sites, bins, &p->lay, &err);
+        s = sdc::build_layout(positions_host, n_sites, bins, tu.segment_pairs, &p->lay, &err);
         if (s != SDC_OK) {
             delete p;
             return set_err(s, err);
@@ -572,6 +584,13 @@ sdc_status sdc_plan_create(const float* positions_host, int64_t n_sites, const s
 #undef TRY
 #undef TRYHIP
     *out = p;
+    return SDC_OK;
+}
+
+sdc_status sdc_plan_get_tuning(const sdc_plan* plan, sdc_tuning* tuning) {
+    g_err.clear();
+    if (!plan || !tuning) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    *tuning = plan->tuning;
     return SDC_OK;
 }
 
@@ -836,6 +855,11 @@ sdc_status sdc_plan_destroy(sdc_plan* p) {
 }
 
 sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t flags, sdc_batch** out) {
+    return sdc_batch_create_tuned(plans, n_plans, flags, nullptr, out);
+}
+
+sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32_t flags, const sdc_tuning* tuning,
+                                  sdc_batch** out) {
     g_err.clear();
     if (!out) return set_err(SDC_ERR_INVALID_ARG, "null output pointer");
     *out = nullptr;
@@ -856,6 +880,21 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t fla
     const int device = plans[0]->device;
     const int prec = plans[0]->corr.precision;
     const int radial = plans[0]->lay.kind == SDC_BINS_RADIAL ? 1 : 0;
+    // Schedule of the one launch: the caller's, else the one the plans' own
+    // tunings give the most work (pair-terms times origins).
+    int schedule = tuning ? tuning->schedule : SDC_SCHED_DEFAULT;
+    if (schedule != SDC_SCHED_DEFAULT) {
+        if (schedule != SDC_SCHED_ONE_PASS && schedule != SDC_SCHED_TWO_PASS)
+            return set_err(SDC_ERR_INVALID_ARG, "unknown schedule");
+        if (!sdc::sched_valid(prec, sdc::sched_index(schedule)))
+            return set_err(SDC_ERR_UNSUPPORTED, "schedule not available for this precision");
+    } else {
+        double w[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < n_plans; ++k)
+            w[plans[k]->tuning.schedule] += (double)plans[k]->lay.n * (double)plans[k]->lay.n *
+                                             plans[k]->corr.n_lags * plans[k]->corr.n_origins;
+        schedule = w[SDC_SCHED_TWO_PASS] > w[SDC_SCHED_ONE_PASS] ? SDC_SCHED_TWO_PASS : SDC_SCHED_ONE_PASS;
+    }
     SDC_HIP(hipSetDevice(device), "hipSetDevice");
     sdc_batch* b = nullptr;
     try {
@@ -874,6 +913,17 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t fla
             }
         }
     }
+    // The launch's task list takes the plans in order of decreasing task
+    // length (K-steps times tile pairs per segment), so the workgroups finish
+    // on the short tasks of the small samples and the launch's tail is short;
+    // the plans keep the caller's order everywhere else.
+    std::vector<int> order((size_t)n_plans);
+    for (int k = 0; k < n_plans; ++k) order[k] = k;
+    auto task_len = [&](int k) {
+        const sdc_plan* p = plans[k];
+        return (double)p->nk * (double)p->lay.pairs.size() / (double)std::max<size_t>(1, p->lay.streams.size());
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return task_len(x) > task_len(y); });
     std::vector<sdc::FusedArgs> args((size_t)n_plans);
     std::vector<int64_t> start((size_t)n_plans + 1, 0);
     int lds = 0;
@@ -881,7 +931,6 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t fla
         sdc_plan* p = plans[k];
         const LagSel* sel = nullptr;
         sdc_status s = get_sel(p, nullptr, 0, &sel);
-        if (s == SDC_OK) s = fused_args(p, *sel, &args[k]);
         if (s != SDC_OK) {
             delete b;
             return s;
@@ -889,6 +938,15 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t fla
         b->plans.push_back(p);
         ++p->batch_refs;
         b->sels.push_back(sel);
+    }
+    for (int k = 0; k < n_plans; ++k) {
+        const int q = order[k];
+        sdc_status s = fused_args(plans[q], *b->sels[q], &args[k]);
+        if (s != SDC_OK) {
+            delete b;
+            return s;
+        }
+        args[k].sched = sdc::sched_index(schedule);
         start[k + 1] = start[k] + (int64_t)args[k].n_groups * args[k].n_streams;
         lds = std::max(lds, sdc::fused_lds_bytes(args[k].win, prec));
     }
@@ -921,8 +979,10 @@ sdc_status sdc_batch_create(sdc_plan* const* plans, int32_t n_plans, int32_t fla
     bl.total = (int)start[n_plans];
     bl.precision = prec;
     bl.radial = radial;
+    bl.sched = sdc::sched_index(schedule);
     bl.lds = lds;
-    const int e = sdc::batch_grid(prec, radial, lds, device, std::max(bl.total, 1), &bl.grid);
+    b->schedule = schedule;
+    const int e = sdc::batch_grid(prec, bl.sched, radial, lds, device, std::max(bl.total, 1), &bl.grid);
     if (e != 0) {
         delete b;
         return hip_err(e, "batch occupancy");
@@ -986,6 +1046,13 @@ sdc_status sdc_batch_info(const sdc_batch* b, int64_t* n_tasks, int32_t* grid) {
     if (!b) return set_err(SDC_ERR_INVALID_ARG, "null batch");
     if (n_tasks) *n_tasks = b->bl.total;
     if (grid) *grid = b->bl.grid;
+    return SDC_OK;
+}
+
+sdc_status sdc_batch_schedule(const sdc_batch* b, int32_t* schedule) {
+    g_err.clear();
+    if (!b || !schedule) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    *schedule = b->schedule;
     return SDC_OK;
 }
 

@@ -15,18 +15,35 @@ namespace sdc {
 // 64 consecutive points in Morton order.  Unused slots are padding (zero
 // spins, no counts).
 constexpr int kTile = 64;
-// Lags handled together by one fused task (consecutive lag indices u).
-// The hi/lo splits take 8: a wave then holds 128 accumulator registers, two
-// workgroups fit on a CU and one workgroup's epilogue overlaps the other's
-// MFMA work.  FP32 takes 16 (one workgroup per CU): its MFMA is 16x slower
-// per flop, so operand reuse across more lags matters more than overlap.
-// The three-piece BF16 form (8 lags) has twice the split's MFMA work per
-// operand load and its operands take 1.5x the registers: it runs with one
-// workgroup per CU and a three-stage register prefetch, as FP32 does.
-constexpr bool one_wg_per_cu(int precision) {
-    return precision == SDC_PREC_FP32 || precision == SDC_PREC_BF16X3;
-}
+// Lags handled together by one fused task (consecutive lag indices u): 8
+// for the reduced-precision forms (128 accumulator registers per wave for
+// one set of sums), 16 for FP32 (its MFMA is 16x slower per flop, so operand
+// reuse across more lags matters more than overlap).
 constexpr int lag_group(int precision) { return precision == SDC_PREC_FP32 ? 16 : 8; }
+// Schedules of the fused product (a tuning choice per plan and batch; the
+// results differ only by rounding).  The small products of the reduced forms
+// always get sums of their own (see the pass constants of the kernel).
+//  kSchedOnePass: every product in one K loop per tile pair; the reduced
+//    forms keep a second accumulator set for the small products (256
+//    registers), so one workgroup fits on a CU; three-stage register
+//    prefetch.  Every precision has it.
+//  kSchedTwoPass: hi/lo splits only: per tile pair one K loop for hi*lo +
+//    lo*hi from zero, then one for hi*hi on top of those sums, in the same
+//    128 registers, then the histogram adds; two workgroups per CU, so one
+//    workgroup's epilogue and memory waits overlap the other's MFMAs.
+constexpr int kSchedOnePass = 0, kSchedTwoPass = 1;
+// Register buffers of the K loops (loads of NS - 1 K-steps ahead in flight).
+// At two workgroups per CU the other workgroup covers the rest of the load
+// latency: two to six buffers in either loop of the two-pass schedule time
+// the same (1085-1102 ms at sc 36^3), so the fewest registers win.
+constexpr int kStagesOnePass = 3, kStagesTwoPassSmall = 2, kStagesTwoPassLarge = 2;
+// Kernel schedule of a public sdc_schedule (ONE_PASS or TWO_PASS).
+constexpr int sched_index(int schedule) { return schedule == SDC_SCHED_TWO_PASS ? kSchedTwoPass : kSchedOnePass; }
+constexpr int wg_per_cu(int sched) { return sched == kSchedTwoPass ? 2 : 1; }
+constexpr bool sched_valid(int precision, int sched) {
+    return sched == kSchedOnePass ||
+           (sched == kSchedTwoPass && (precision == SDC_PREC_SPLIT_BF16 || precision == SDC_PREC_SPLIT_FP16));
+}
 // Pack elements (8 samples each) in one lane's B window: LG - 1 + 8 samples.
 constexpr int win_blocks(int lg) { return (lg + 14) / 8; }
 // Origins per pack block; a K-step of the fused product takes two blocks
@@ -77,9 +94,24 @@ struct Layout {
 // Records the thread-local error text returned by sdc_last_error(); returns s.
 sdc_status set_error(sdc_status s, const std::string& msg);
 
-// Builds the tile layout of a sample.  Returns SDC_OK or an error with text.
-sdc_status build_layout(const float* pos, int64_t n, const sdc_bin_spec* spec,
+// Builds the tile layout of a sample, streams cut into segments of at most
+// segment_pairs tile pairs.  Returns SDC_OK or an error with text.
+sdc_status build_layout(const float* pos, int64_t n, const sdc_bin_spec* spec, int segment_pairs,
                         Layout* out, std::string* err);
+
+// Default tile pairs per fused task: periodic streams cut into segments of
+// 96 pairs, radial streams (all j-tiles of an i-tile) whole.
+constexpr int kDefaultSegmentPeriodic = 96;
+constexpr int kMaxSegmentPairs = 1 << 20;
+constexpr int default_segment_pairs(int kind) {
+    return kind == SDC_BINS_RADIAL ? kMaxSegmentPairs : kDefaultSegmentPeriodic;
+}
+
+// Tuning a plan runs with (sdc_tune.cpp): the caller's fields where set,
+// else the entry of the tuning file named by SDC_TUNING_FILE for the plan's
+// size class, else the defaults.  Every field of *out is set (no zeros).
+sdc_status resolve_tuning(const sdc_tuning* given, int64_t n_sites, const sdc_bin_spec* bins,
+                          const sdc_corr_spec* corr, int device, sdc_tuning* out);
 
 // Global bin of window coordinate w of stream s (periodic kinds).
 int64_t window_bin(const Layout& lay, const KStream& s, int w);
@@ -179,6 +211,7 @@ struct FusedArgs {
     int64_t n_bins;
     int stride;
     int precision;
+    int sched;                     // kSchedOnePass / kSchedTwoPass
 };
 int launch_fused(const FusedArgs& a, void* stream);
 
@@ -191,13 +224,13 @@ struct BatchLaunch {
     int n_plans;
     unsigned* queue;
     int total;
-    int precision, radial;
+    int precision, radial, sched;
     int lds, grid;
 };
 int launch_fused_batch(const BatchLaunch& b, void* stream);
 // Workgroups that fit on the device at once (a multiple of 8, at most `total`
-// rounded up to 8); also sets the kernel's dynamic LDS limit.
-int batch_grid(int precision, int radial, int lds, int device, int total, int* grid);
+// rounded up to 8).
+int batch_grid(int precision, int sched, int radial, int lds, int device, int total, int* grid);
 
 struct CountArgs {
     const KPair* pairs;
@@ -316,6 +349,7 @@ int launch_sq_finalize(const double* raw, const double* n_org, int64_t n_sites, 
 
 int launch_zero(void* ptr, int64_t bytes, void* stream);
 
+
 // Deterministic mode: every sum that several threads add into is kept as a
 // two's-complement 64-bit fixed-point number with 2^-20 resolution, so
 // integer atomics make the result independent of the order of the adds.
@@ -340,6 +374,8 @@ struct TrajArgs {
     float* work;               // [5][n][3] fp32 scratch: S, T, acc, k
 };
 int launch_traj(const TrajArgs& a, void* stream);
+// Seeded independent uniform unit vectors, [n_frames][n][3] fp32.
+int launch_unit_spins(float* out, int64_t n, int64_t n_frames, uint64_t seed, void* stream);
 
 // Metropolis sweeps (sdc_mc.hip).
 struct McArgs {

@@ -211,22 +211,44 @@ __device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
     }
 }
 
+// Products one K loop forms (PASS):
+//  kPassAll   : every product of the form; the large ones into acc.v, the
+//               small ones into acc.s (one-pass schedule);
+//  kPassSmall : hi*lo + lo*hi into acc.v (first loop of the two-pass
+//               schedule, from zero);
+//  kPassLarge : hi*hi into acc.v (second loop, on top of the small sums).
+// The small products are never added to a sum that already holds the large
+// ones: the BF16/FP16 matrix cores align every addend of an instruction to
+// the largest one and drop the bits that fall below a fixed window, always
+// downwards, so the low bits of small products added to a large sum would
+// bias each element by a fraction of its last place per K-step.  Added to a
+// sum of their own size they keep every bit, and the large products added
+// afterwards (16 significant bits each) lose none either.
+constexpr int kPassAll = 0, kPassLarge = 1, kPassSmall = 2;
+
 // Three-product split for lag u0 + M: hi*hi + hi*lo + lo*hi.
-template <int PREC, int M, int NW, int LG>
+template <int PREC, int PASS, int M, int NW, int LG>
 __device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[NW],
-                                  const uint32_t (&wl)[NW], f32x16 (&acc)[LG]) {
+                                  const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG]) {
     const uint4 bh = slice8<M, NW>(wh);
-    const uint4 bl = slice8<M, NW>(wl);
-    acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
-    acc[M] = mfma16<PREC>(av.x, bl, acc[M]);
-    acc[M] = mfma16<PREC>(av.y, bh, acc[M]);
+    if constexpr (PASS == kPassLarge) {
+        acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
+    } else {
+        const uint4 bl = slice8<M, NW>(wl);
+        if constexpr (PASS == kPassAll) {
+            acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
+            acc_s[M] = mfma16<PREC>(av.x, bl, acc_s[M]);
+            acc_s[M] = mfma16<PREC>(av.y, bh, acc_s[M]);
+        } else {
+            acc[M] = mfma16<PREC>(av.x, bl, acc[M]);
+            acc[M] = mfma16<PREC>(av.y, bh, acc[M]);
+        }
+    }
 }
 
 // Three-piece BF16 for lag u0 + M: the six products hh, hm, mh, mm, hl, lh
-// (the dropped ml, lm, ll are below 2^-24 of the product).  The products of
-// order 2^-16 (mm, hl, lh) go to an accumulator of their own: added to the
-// large one they would fall below its last bit, where the matrix cores'
-// accumulation rounding is not unbiased.
+// (the dropped ml, lm, ll are below 2^-24 of the product); hh goes to the
+// main accumulator, the other five (2^-8 and smaller) to the second one.
 template <int M, int NW, int LG>
 __device__ inline void x3_step(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
                                const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG]) {
@@ -234,8 +256,8 @@ __device__ inline void x3_step(const Chunk3& av, const uint32_t (&wh)[NW], const
     const uint4 bm = slice8<M, NW>(wm);
     const uint4 bl = slice8<M, NW>(wl);
     acc[M] = mfma16<SDC_PREC_BF16X3>(av.x, bh, acc[M]);
-    acc[M] = mfma16<SDC_PREC_BF16X3>(av.x, bm, acc[M]);
-    acc[M] = mfma16<SDC_PREC_BF16X3>(av.y, bh, acc[M]);
+    acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.x, bm, acc_s[M]);
+    acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.y, bh, acc_s[M]);
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.y, bm, acc_s[M]);
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.x, bl, acc_s[M]);
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.z, bh, acc_s[M]);
@@ -248,10 +270,10 @@ __device__ inline void x3_all(const Chunk3& av, const uint32_t (&wh)[NW], const 
     (x3_step<Ms, NW, LG>(av, wh, wm, wl, acc, acc_s), ...);
 }
 
-template <int PREC, int NW, int LG, int... Ms>
+template <int PREC, int PASS, int NW, int LG, int... Ms>
 __device__ inline void split_all(const Chunk& av, const uint32_t (&wh)[NW], const uint32_t (&wl)[NW],
-                                 f32x16 (&acc)[LG], std::integer_sequence<int, Ms...>) {
-    (split_step<PREC, Ms, NW, LG>(av, wh, wl, acc), ...);
+                                 f32x16 (&acc)[LG], f32x16 (&acc_s)[LG], std::integer_sequence<int, Ms...>) {
+    (split_step<PREC, PASS, Ms, NW, LG>(av, wh, wl, acc, acc_s), ...);
 }
 
 // FP32: MFMA q of the K-step takes origin 16c + 8h + q on both sides.
@@ -280,24 +302,24 @@ __device__ inline int pmod_dev(int a, int m) {
     return r < 0 ? r + m : r;
 }
 
-// Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
-// B window of NB pack elements.
-// Accumulators of one wave: LG 32x32 tiles, and for the three-piece form a
-// second set for its small products.
-template <int PREC, int LG>
+// Accumulators of one wave: LG 32x32 tiles, and for the one-pass schedule
+// of the reduced-precision forms a second set for their small products.
+template <int PREC, int SCHED, int LG>
 struct Acc {
     f32x16 v[LG];
-    f32x16 s[PREC == SDC_PREC_BF16X3 ? LG : 1];
+    f32x16 s[(PREC == SDC_PREC_FP32 || SCHED == kSchedTwoPass) ? 1 : LG];
 };
 
+// Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
+// B window of NB pack elements.
 template <int PREC, int NB>
 struct Stage {
     PackElem<PREC> a;
     PackElem<PREC> b[NB];
 };
 
-template <int PREC, int NB, int LG>
-__device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, LG>& ac) {
+template <int PREC, int PASS, int SCHED, int NB, int LG>
+__device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LG>& ac) {
     f32x16 (&acc)[LG] = ac.v;
     constexpr int NW = 4 * NB;
     if constexpr (PREC == SDC_PREC_BF16X3) {
@@ -341,12 +363,38 @@ __device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, LG>& ac) {
             wl[4 * k + 2] = s.b[k].y.z;
             wl[4 * k + 3] = s.b[k].y.w;
         }
-        split_all<PREC, NW, LG>(s.a, wh, wl, acc, std::make_integer_sequence<int, LG>{});
+        // the two-pass schedule has no second accumulator set (its passes
+        // never write one)
+        if constexpr (SCHED == kSchedTwoPass)
+            split_all<PREC, PASS, NW, LG>(s.a, wh, wl, acc, acc, std::make_integer_sequence<int, LG>{});
+        else
+            split_all<PREC, PASS, NW, LG>(s.a, wh, wl, acc, ac.s, std::make_integer_sequence<int, LG>{});
     }
 }
 
 int fused_lds_bytes(int win, int precision) {
     return lag_group(precision) * win * (int)sizeof(double) + 1024 * (int)sizeof(float);
+}
+
+// One K loop over all K-steps of a tile pair with NS register buffers: the
+// loads of the next NS - 1 K-steps are in flight while one step's MFMAs run
+// (load indices clamp to the last step, so the last round's extra loads are
+// harmless re-reads).  The scheduling barriers keep the loads ahead of the
+// MFMAs.
+template <int PREC, int PASS, int SCHED, int NB, int LG, int NS, class Load>
+__device__ __forceinline__ void k_loop(int nk, const Load& load, Acc<PREC, SCHED, LG>& acc) {
+    Stage<PREC, NB> s[NS];
+#pragma unroll
+    for (int j = 0; j < NS - 1; ++j) load(s[j], j);
+    for (int kk = 0; kk < nk; kk += NS) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            load(s[(j + NS - 1) % NS], kk + j + NS - 1);
+            __builtin_amdgcn_sched_barrier(0);
+            if (j == 0 || kk + j < nk) stage_mma<PREC, PASS, SCHED, NB, LG>(s[j], acc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
 }
 
 // One task of a plan: the stream's tile pairs for one lag group, histogram
@@ -356,10 +404,13 @@ int fused_lds_bytes(int win, int precision) {
 // component and the block offsets follow from the step with one scalar
 // division; otherwise the blocks of all components are taken in turn and a
 // step may straddle two components.
-template <int PREC, int RADIAL, int PAIRED>
+// SCHED: kSchedOnePass or kSchedTwoPass (hi/lo splits only), see k_loop and
+// the pass constants.
+template <int PREC, int RADIAL, int PAIRED, int SCHED>
 __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double* hist) {
     constexpr int LG = lag_group(PREC);
     constexpr int NB = win_blocks(LG);
+    constexpr bool TWO = SCHED == kSchedTwoPass;
     float* e2s = (float*)(hist + LG * a.win);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -389,12 +440,12 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         const KPair pr = a.pairs[p];
         const int64_t si = (int64_t)pr.ti * kTile + wi * 32 + l32;
         const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
-        Acc<PREC, LG> acc;
+        Acc<PREC, SCHED, LG> acc;
 #pragma unroll
         for (int m = 0; m < LG; ++m)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc.v[m][r] = 0.0f;
-        if constexpr (PREC == SDC_PREC_BF16X3) {
+        if constexpr (PREC != SDC_PREC_FP32 && !TWO) {
 #pragma unroll
             for (int m = 0; m < LG; ++m)
 #pragma unroll
@@ -402,7 +453,8 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         }
 
         // Register buffers: while K-step kk is multiplied the loads of later
-        // steps are in flight (indices clamp to the last block).
+        // steps are in flight (indices clamp to the last block).  Parts of
+        // an element a pass does not use are not loaded (dead loads).
         auto load = [&](Stage<PREC, NB>& b, int kk) {
             kk = kk < nk ? kk : nk - 1;
             const Elem* pb;
@@ -423,86 +475,65 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
 #pragma unroll
             for (int q = 0; q < NB; ++q) b.b[q] = pb[q * a.n_pad];
         };
-        if constexpr (one_wg_per_cu(PREC)) {
-            // One wave per SIMD: three buffers keep two K-steps of loads in
-            // flight (the last round stops at nk); the scheduling barriers
-            // keep loads ahead of the MFMAs.
-            Stage<PREC, NB> s0, s1, s2;
-            load(s0, 0);
-            load(s1, 1);
-            for (int kk = 0; kk < nk; kk += 3) {
-                load(s2, kk + 2);
-                __builtin_amdgcn_sched_barrier(0);
-                stage_mma<PREC, NB, LG>(s0, acc);
-                __builtin_amdgcn_sched_barrier(0);
-                load(s0, kk + 3);
-                __builtin_amdgcn_sched_barrier(0);
-                if (kk + 1 < nk) stage_mma<PREC, NB, LG>(s1, acc);
-                __builtin_amdgcn_sched_barrier(0);
-                load(s1, kk + 4);
-                __builtin_amdgcn_sched_barrier(0);
-                if (kk + 2 < nk) stage_mma<PREC, NB, LG>(s2, acc);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
-            // Two waves per SIMD: two buffers; the other wave covers the rest
-            // of the load latency.
-            Stage<PREC, NB> s0, s1;
-            load(s0, 0);
-            for (int kk = 0; kk < nk; kk += 2) {
-                load(s1, kk + 1);
-                __builtin_amdgcn_sched_barrier(0);
-                stage_mma<PREC, NB, LG>(s0, acc);
-                __builtin_amdgcn_sched_barrier(0);
-                if (kk + 1 < nk) {
-                    load(s0, kk + 2);
-                    __builtin_amdgcn_sched_barrier(0);
-                    stage_mma<PREC, NB, LG>(s1, acc);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
 
         // Epilogue: bin of each accumulator element, LDS FP64 add per lag.
         // Accumulator register r of lane (l32, h) holds row 8(r/4) + 4h + r%4,
         // column l32 of the wave's 32x32 quadrant.
-        const int64_t rowbase = (int64_t)pr.ti * kTile + wi * 32 + 4 * h;
         int bin[16];
-        if constexpr (RADIAL) {
-            if (a.keys) {
-                // the pair's shells, computed once per plan for all lag groups
-                const uint4* kp = (const uint4*)(a.keys + (((int64_t)p * 4 + wave) * 64 + lane) * 16);
-                const uint4 k0 = kp[0], k1 = kp[1];
-                const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+        auto bins = [&]() {
+            const int64_t rowbase = (int64_t)pr.ti * kTile + wi * 32 + 4 * h;
+            if constexpr (RADIAL) {
+                if (a.keys) {
+                    // the pair's shells, computed once per plan for all lag groups
+                    const uint4* kp = (const uint4*)(a.keys + (((int64_t)p * 4 + wave) * 64 + lane) * 16);
+                    const uint4 k0 = kp[0], k1 = kp[1];
+                    const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
 #pragma unroll
-                for (int r = 0; r < 16; ++r) bin[r] = (int)((kw[r / 2] >> (16 * (r & 1))) & 0xFFFFu);
+                    for (int r = 0; r < 16; ++r) bin[r] = (int)((kw[r / 2] >> (16 * (r & 1))) & 0xFFFFu);
+                } else {
+                    const float4 pj = *(const float4*)(a.pos4 + 4 * sj);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float4 pi = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
+                        const float d2 = dist2_f32(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
+                        bin[r] = shell_of(d2, e2s, a.n_shells, a.inv_w);
+                    }
+                }
             } else {
-                const float4 pj = *(const float4*)(a.pos4 + 4 * sj);
+                const int gj = a.gtab[sj] + pr.shift;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float4 pi = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
-                    const float d2 = dist2_f32(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
-                    bin[r] = shell_of(d2, e2s, a.n_shells, a.inv_w);
+                for (int r = 0; r < 16; ++r) bin[r] = gj - a.gtab[rowbase + 8 * (r / 4) + (r % 4)];
+            }
+        };
+        auto add_hist = [&](auto with_small) {
+#pragma unroll
+            for (int m = 0; m < LG; ++m) {
+                if ((grp.mask >> m) & 1) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        double v = (double)acc.v[m][r];
+                        if constexpr (decltype(with_small)::value) v += (double)acc.s[m][r];
+                        if (a.det)
+                            atomicAdd(reinterpret_cast<unsigned long long*>(hist) + m * a.win + bin[r],
+                                      to_fixed(v));
+                        else
+                            atomicAdd(&hist[m * a.win + bin[r]], v);
+                    }
                 }
             }
+        };
+
+        if constexpr (TWO) {
+            // small products first, while the sums are still small, then the
+            // large ones on top (see the pass constants)
+            k_loop<PREC, kPassSmall, SCHED, NB, LG, kStagesTwoPassSmall>(nk, load, acc);
+            k_loop<PREC, kPassLarge, SCHED, NB, LG, kStagesTwoPassLarge>(nk, load, acc);
+            bins();
+            add_hist(std::false_type{});
         } else {
-            const int gj = a.gtab[sj] + pr.shift;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) bin[r] = gj - a.gtab[rowbase + 8 * (r / 4) + (r % 4)];
-        }
-#pragma unroll
-        for (int m = 0; m < LG; ++m) {
-            if ((grp.mask >> m) & 1) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    double v = (double)acc.v[m][r];
-                    if constexpr (PREC == SDC_PREC_BF16X3) v += (double)acc.s[m][r];
-                    if (a.det)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(hist) + m * a.win + bin[r], to_fixed(v));
-                    else
-                        atomicAdd(&hist[m * a.win + bin[r]], v);
-                }
-            }
+            k_loop<PREC, kPassAll, SCHED, NB, LG, kStagesOnePass>(nk, load, acc);
+            bins();
+            add_hist(std::integral_constant<bool, PREC != SDC_PREC_FP32>{});
         }
     }
     __syncthreads();
@@ -536,8 +567,8 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
     }
 }
 
-template <int PREC, int RADIAL, int PAIRED>
-__global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_kernel(FusedArgs a) {
+template <int PREC, int RADIAL, int PAIRED, int SCHED>
+__global__ __launch_bounds__(256, wg_per_cu(SCHED)) void fused_kernel(FusedArgs a) {
     extern __shared__ double hist[];
     // XCD-aware task order: consecutive tasks land on the same XCD (work-
     // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
@@ -548,7 +579,7 @@ __global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_kernel
     const int per = (n_tasks + 7) / 8;
     const int task = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (task >= n_tasks) return;
-    fused_task<PREC, RADIAL, PAIRED>(a, task, hist);
+    fused_task<PREC, RADIAL, PAIRED, SCHED>(a, task, hist);
 }
 
 // Persistent kernel over the tasks of several plans (one launch for a
@@ -557,9 +588,11 @@ __global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_kernel
 // workgroup takes tasks from its own XCD's queue with an atomic counter and,
 // once that queue is empty, from the following queues in turn.  Every
 // counter only grows and each queue is visited until it is found empty, so
-// every workgroup leaves the loop after at most total + 8 claims.
-template <int PREC, int RADIAL>
-__global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_batch_kernel(
+// every workgroup leaves the loop after at most total + 8 claims.  The
+// K-step addressing follows each plan's origin-block count (per component
+// when it is even).
+template <int PREC, int RADIAL, int SCHED>
+__global__ __launch_bounds__(256, wg_per_cu(SCHED)) void fused_batch_kernel(
     const FusedArgs* __restrict__ args, const int64_t* __restrict__ task_start, int n_plans,
     unsigned* __restrict__ queue, int per, int total) {
     extern __shared__ double hist[];
@@ -607,62 +640,68 @@ __global__ __launch_bounds__(256, one_wg_per_cu(PREC) ? 1 : 2) void fused_batch_
         const int pl = __builtin_amdgcn_readfirstlane(s_plan);
         __syncthreads();
         if (task < 0) break;
-        fused_task<PREC, RADIAL, 0>(args[pl], task, hist);  // plans of a batch differ in O8
+        const int paired = __builtin_amdgcn_readfirstlane(args[pl].O8 % 2 == 0);
+        if (paired)
+            fused_task<PREC, RADIAL, 1, SCHED>(args[pl], task, hist);
+        else
+            fused_task<PREC, RADIAL, 0, SCHED>(args[pl], task, hist);
         __syncthreads();  // the histogram is reused by the next task
     }
 }
 
-template <int PREC>
-static int launch_fused_prec(const FusedArgs& a, hipStream_t s) {
-    const int lds = fused_lds_bytes(a.win, PREC);
-    const int n_tasks = a.n_groups * a.n_streams;
-    const int grid = 8 * ((n_tasks + 7) / 8);
-    const bool paired = a.O8 % 2 == 0;
-    if (a.kind == SDC_BINS_RADIAL) {
-        if (paired)
-            hipLaunchKernelGGL((fused_kernel<PREC, 1, 1>), dim3(grid), dim3(256), lds, s, a);
-        else
-            hipLaunchKernelGGL((fused_kernel<PREC, 1, 0>), dim3(grid), dim3(256), lds, s, a);
-    } else {
-        if (paired)
-            hipLaunchKernelGGL((fused_kernel<PREC, 0, 1>), dim3(grid), dim3(256), lds, s, a);
-        else
-            hipLaunchKernelGGL((fused_kernel<PREC, 0, 0>), dim3(grid), dim3(256), lds, s, a);
-    }
-    return (int)hipGetLastError();
+// Instantiated kernels: (precision, schedule) pairs the library runs.
+template <int PREC, int SCHED, int RADIAL, int PAIRED>
+static const void* fused_fn() {
+    return (const void*)fused_kernel<PREC, RADIAL, PAIRED, SCHED>;
 }
-
-int launch_fused(const FusedArgs& a, void* stream) {
-    if (a.n_groups * a.n_streams == 0) return 0;
-    hipStream_t s = (hipStream_t)stream;
-    switch (a.precision) {
-        case SDC_PREC_FP32: return launch_fused_prec<SDC_PREC_FP32>(a, s);
-        case SDC_PREC_SPLIT_BF16: return launch_fused_prec<SDC_PREC_SPLIT_BF16>(a, s);
-        case SDC_PREC_SPLIT_FP16: return launch_fused_prec<SDC_PREC_SPLIT_FP16>(a, s);
-        case SDC_PREC_BF16X3: return launch_fused_prec<SDC_PREC_BF16X3>(a, s);
-        default: return (int)hipErrorInvalidValue;
-    }
-}
-
-template <int PREC, int RADIAL>
+template <int PREC, int SCHED, int RADIAL>
 static const void* batch_fn() {
-    return (const void*)fused_batch_kernel<PREC, RADIAL>;
+    return (const void*)fused_batch_kernel<PREC, RADIAL, SCHED>;
 }
 
-static const void* batch_kernel_of(int precision, int radial) {
+template <int PREC, int SCHED>
+static const void* pick_fused(int radial, int paired, bool batch) {
+    if (batch) return radial ? batch_fn<PREC, SCHED, 1>() : batch_fn<PREC, SCHED, 0>();
+    if (radial) return paired ? fused_fn<PREC, SCHED, 1, 1>() : fused_fn<PREC, SCHED, 1, 0>();
+    return paired ? fused_fn<PREC, SCHED, 0, 1>() : fused_fn<PREC, SCHED, 0, 0>();
+}
+
+// Kernel of a fused launch, or null for a (precision, schedule) pair that
+// does not exist.
+static const void* fused_kernel_of(int precision, int sched, int radial, int paired, bool batch) {
     switch (precision) {
-        case SDC_PREC_FP32: return radial ? batch_fn<SDC_PREC_FP32, 1>() : batch_fn<SDC_PREC_FP32, 0>();
+        case SDC_PREC_FP32:
+            return sched == kSchedOnePass ? pick_fused<SDC_PREC_FP32, kSchedOnePass>(radial, paired, batch)
+                                          : nullptr;
+        case SDC_PREC_BF16X3:
+            return sched == kSchedOnePass ? pick_fused<SDC_PREC_BF16X3, kSchedOnePass>(radial, paired, batch)
+                                          : nullptr;
         case SDC_PREC_SPLIT_BF16:
-            return radial ? batch_fn<SDC_PREC_SPLIT_BF16, 1>() : batch_fn<SDC_PREC_SPLIT_BF16, 0>();
+            return sched == kSchedOnePass
+                       ? pick_fused<SDC_PREC_SPLIT_BF16, kSchedOnePass>(radial, paired, batch)
+                       : pick_fused<SDC_PREC_SPLIT_BF16, kSchedTwoPass>(radial, paired, batch);
         case SDC_PREC_SPLIT_FP16:
-            return radial ? batch_fn<SDC_PREC_SPLIT_FP16, 1>() : batch_fn<SDC_PREC_SPLIT_FP16, 0>();
-        case SDC_PREC_BF16X3: return radial ? batch_fn<SDC_PREC_BF16X3, 1>() : batch_fn<SDC_PREC_BF16X3, 0>();
+            return sched == kSchedOnePass
+                       ? pick_fused<SDC_PREC_SPLIT_FP16, kSchedOnePass>(radial, paired, batch)
+                       : pick_fused<SDC_PREC_SPLIT_FP16, kSchedTwoPass>(radial, paired, batch);
         default: return nullptr;
     }
 }
 
-int batch_grid(int precision, int radial, int lds, int device, int total, int* grid) {
-    const void* fn = batch_kernel_of(precision, radial);
+int launch_fused(const FusedArgs& a, void* stream) {
+    if (a.n_groups * a.n_streams == 0) return 0;
+    if (!sched_valid(a.precision, a.sched)) return (int)hipErrorInvalidValue;
+    const void* fn = fused_kernel_of(a.precision, a.sched, a.kind == SDC_BINS_RADIAL, a.O8 % 2 == 0, false);
+    if (!fn) return (int)hipErrorInvalidValue;
+    const int lds = fused_lds_bytes(a.win, a.precision);
+    const int n_tasks = a.n_groups * a.n_streams;
+    const int grid = 8 * ((n_tasks + 7) / 8);
+    void* params[] = {(void*)&a};
+    return (int)hipLaunchKernel(fn, dim3(grid), dim3(256), params, lds, (hipStream_t)stream);
+}
+
+int batch_grid(int precision, int sched, int radial, int lds, int device, int total, int* grid) {
+    const void* fn = fused_kernel_of(precision, sched, radial, 0, true);
     if (!fn) return (int)hipErrorInvalidValue;
     int per_cu = 0, n_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
@@ -679,34 +718,19 @@ int batch_grid(int precision, int radial, int lds, int device, int total, int* g
 
 int launch_fused_batch(const BatchLaunch& b, void* stream) {
     if (b.total == 0) return 0;
-    hipStream_t s = (hipStream_t)stream;
+    const void* fn = fused_kernel_of(b.precision, b.sched, b.radial, 0, true);
+    if (!fn) return (int)hipErrorInvalidValue;
     int e = launch_zero(b.queue, 8 * sizeof(unsigned), stream);
     if (e != 0) return e;
-    const int per = (b.total + 7) / 8;
-#define SDC_BATCH(P, R)                                                                                      \
-    hipLaunchKernelGGL((fused_batch_kernel<P, R>), dim3(b.grid), dim3(256), b.lds, s, b.args, b.task_start, \
-                       b.n_plans, b.queue, per, b.total)
-    switch (b.precision) {
-        case SDC_PREC_FP32:
-            if (b.radial) SDC_BATCH(SDC_PREC_FP32, 1);
-            else SDC_BATCH(SDC_PREC_FP32, 0);
-            break;
-        case SDC_PREC_SPLIT_BF16:
-            if (b.radial) SDC_BATCH(SDC_PREC_SPLIT_BF16, 1);
-            else SDC_BATCH(SDC_PREC_SPLIT_BF16, 0);
-            break;
-        case SDC_PREC_SPLIT_FP16:
-            if (b.radial) SDC_BATCH(SDC_PREC_SPLIT_FP16, 1);
-            else SDC_BATCH(SDC_PREC_SPLIT_FP16, 0);
-            break;
-        case SDC_PREC_BF16X3:
-            if (b.radial) SDC_BATCH(SDC_PREC_BF16X3, 1);
-            else SDC_BATCH(SDC_PREC_BF16X3, 0);
-            break;
-        default: return (int)hipErrorInvalidValue;
-    }
-#undef SDC_BATCH
-    return (int)hipGetLastError();
+    int per = (b.total + 7) / 8;
+    const FusedArgs* args = b.args;
+    const int64_t* task_start = b.task_start;
+    int n_plans = b.n_plans;
+    unsigned* queue = b.queue;
+    int total = b.total;
+    void* params[] = {(void*)&args, (void*)&task_start, (void*)&n_plans, (void*)&queue, (void*)&per,
+                      (void*)&total};
+    return (int)hipLaunchKernel(fn, dim3(b.grid), dim3(256), params, b.lds, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1041,23 +1065,16 @@ int launch_self(const SelfArgs& a, void* stream) {
 // once per device at plan creation so that the launch paths make no attribute
 // calls (they stay legal under stream capture).
 int prepare_kernels() {
-    const void* fused[] = {
-        (const void*)fused_kernel<SDC_PREC_FP32, 0, 0>,       (const void*)fused_kernel<SDC_PREC_FP32, 1, 0>,
-        (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0, 0>, (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1, 0>,
-        (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0, 0>, (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1, 0>,
-        (const void*)fused_kernel<SDC_PREC_BF16X3, 0, 0>,     (const void*)fused_kernel<SDC_PREC_BF16X3, 1, 0>,
-        (const void*)fused_kernel<SDC_PREC_FP32, 0, 1>,       (const void*)fused_kernel<SDC_PREC_FP32, 1, 1>,
-        (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 0, 1>, (const void*)fused_kernel<SDC_PREC_SPLIT_BF16, 1, 1>,
-        (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 0, 1>, (const void*)fused_kernel<SDC_PREC_SPLIT_FP16, 1, 1>,
-        (const void*)fused_kernel<SDC_PREC_BF16X3, 0, 1>,     (const void*)fused_kernel<SDC_PREC_BF16X3, 1, 1>,
-        batch_fn<SDC_PREC_FP32, 0>(),                       batch_fn<SDC_PREC_FP32, 1>(),
-        batch_fn<SDC_PREC_SPLIT_BF16, 0>(),                 batch_fn<SDC_PREC_SPLIT_BF16, 1>(),
-        batch_fn<SDC_PREC_SPLIT_FP16, 0>(),                 batch_fn<SDC_PREC_SPLIT_FP16, 1>(),
-        batch_fn<SDC_PREC_BF16X3, 0>(),                     batch_fn<SDC_PREC_BF16X3, 1>()};
-    for (const void* f : fused) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxFusedLds);
-        if (e != hipSuccess) return (int)e;
-    }
+    for (int prec = SDC_PREC_FP32; prec <= SDC_PREC_BF16X3; ++prec)
+        for (int sched = kSchedOnePass; sched <= kSchedTwoPass; ++sched)
+            for (int k = 0; k < 6; ++k) {  // (radial, paired) of the single-plan kernels, then the batch ones
+                const bool batch = k >= 4;
+                const int radial = batch ? (k & 1) : ((k >> 1) & 1), paired = batch ? 0 : (k & 1);
+                const void* f = fused_kernel_of(prec, sched, radial, paired, batch);
+                if (!f) continue;
+                hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxFusedLds);
+                if (e != hipSuccess) return (int)e;
+            }
     const void* self[] = {(const void*)self_kernel<true, SDC_PREC_FP32>,
                           (const void*)self_kernel<true, SDC_PREC_SPLIT_BF16>,
                           (const void*)self_kernel<true, SDC_PREC_SPLIT_FP16>,
@@ -1255,6 +1272,36 @@ int launch_zero(void* ptr, int64_t bytes, void* stream) {
 // ---------------------------------------------------------------------------
 
 __device__ inline float u24(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+// Independent uniform unit vectors for every (frame, site): Philox4x32-10,
+// key = seed, counter = (site low, frame, site high, 7); z = 2u0 - 1,
+// phi = 2 pi u1 (the autotuner's input; any spins time the same).
+__global__ void unit_spins_kernel(float* __restrict__ out, int64_t n, int64_t n_frames, uint64_t seed) {
+    const int64_t total = n * n_frames;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t f = x / n, i = x - f * n;
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)f, (uint32_t)((uint64_t)i >> 32), 7u};
+        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double z = 2.0 * ((double)(c[0] >> 8) * (1.0 / 16777216.0)) - 1.0;
+        const double r = sqrt(fmax(0.0, 1.0 - z * z));
+        double sn, cs;
+        sincospi(2.0 * ((double)(c[1] >> 8) * (1.0 / 16777216.0)), &sn, &cs);
+        out[3 * x] = (float)(r * cs);
+        out[3 * x + 1] = (float)(r * sn);
+        out[3 * x + 2] = (float)z;
+    }
+}
+
+int launch_unit_spins(float* out, int64_t n, int64_t n_frames, uint64_t seed, void* stream) {
+    const int64_t total = n * n_frames;
+    if (total <= 0) return 0;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(unit_spins_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, out, n,
+                       n_frames, seed);
+    return (int)hipGetLastError();
+}
 
 __global__ void traj_init_kernel(TrajArgs a, float* S) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

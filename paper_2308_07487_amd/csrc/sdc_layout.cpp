@@ -83,19 +83,17 @@ uint64_t spread3(uint64_t v) {
     return v;
 }
 
-// Cut every stream into consecutive segments of at most kStreamSegment pairs
-// (same window, same bins).  The lag groups of a segment run as neighbouring
-// tasks on one XCD and share its operands in L2 only while they are in step;
-// over a whole stream (up to ~1000 pairs) they drift apart and the operand
-// re-reads miss L2.  Segments of ~100 pairs cut the L2 misses ~3x at the
-// price of ~8x more histogram merges (still < 1% of the work).
-constexpr int kStreamSegment = 96;
-
-void split_streams(Layout* lay) {
+// Cut every stream into consecutive segments of at most `seg` pairs (same
+// window, same bins).  The lag groups of a segment run as neighbouring tasks
+// on one XCD and share its operands in L2 only while they are in step; over
+// a whole stream (up to ~1000 pairs) they drift apart and the operand
+// re-reads miss L2.  Shorter segments keep them in step at the price of
+// more histogram merges (one per segment, lag group and window bin).
+void split_streams(Layout* lay, int seg) {
     std::vector<KStream> out;
     for (const KStream& s : lay->streams) {
         const int len = s.p1 - s.p0;
-        const int nseg = (len + kStreamSegment - 1) / kStreamSegment;
+        const int nseg = (len + seg - 1) / seg;
         for (int k = 0; k < nseg; ++k) {
             KStream t = s;
             t.p0 = s.p0 + (int)((int64_t)k * len / nseg);
@@ -106,7 +104,7 @@ void split_streams(Layout* lay) {
     lay->streams.swap(out);
 }
 
-sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec, Layout* lay,
+sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec, int seg, Layout* lay,
                           std::string* err) {
     const bool bcc = spec->kind == SDC_BINS_PERIODIC_BCC;
     const int nsub = bcc ? 2 : 1;
@@ -237,11 +235,11 @@ sdc_status build_periodic(const float* pos, int64_t n, const sdc_bin_spec* spec,
                         s.p1 = (int32_t)lay->pairs.size();
                         lay->streams.push_back(s);
                     }
-    split_streams(lay);
+    split_streams(lay, seg);
     return SDC_OK;
 }
 
-sdc_status build_radial(const float* pos, int64_t n, const sdc_bin_spec* spec, Layout* lay,
+sdc_status build_radial(const float* pos, int64_t n, const sdc_bin_spec* spec, int seg, Layout* lay,
                         std::string* err) {
     if (spec->n_shells < 1 || spec->n_shells > 1024)
         return fail(err, spec->n_shells < 1 ? SDC_ERR_INVALID_ARG : SDC_ERR_UNSUPPORTED,
@@ -297,14 +295,16 @@ sdc_status build_radial(const float* pos, int64_t n, const sdc_bin_spec* spec, L
         s.p1 = (int32_t)lay->pairs.size();
         lay->streams.push_back(s);
     }
+    split_streams(lay, seg);
     return SDC_OK;
 }
 
 }  // namespace
 
-sdc_status build_layout(const float* pos, int64_t n, const sdc_bin_spec* spec, Layout* lay,
+sdc_status build_layout(const float* pos, int64_t n, const sdc_bin_spec* spec, int segment_pairs, Layout* lay,
                         std::string* err) {
     if (!pos || !spec || !lay) return fail(err, SDC_ERR_INVALID_ARG, "null pointer");
+    if (segment_pairs < 1) return fail(err, SDC_ERR_INVALID_ARG, "segment_pairs must be >= 1");
     if (n < 1) return fail(err, SDC_ERR_INVALID_ARG, "n_sites must be >= 1");
     if (n > (int64_t)1 << 26) return fail(err, SDC_ERR_UNSUPPORTED, "n_sites above 2^26");
     *lay = Layout();
@@ -312,9 +312,9 @@ sdc_status build_layout(const float* pos, int64_t n, const sdc_bin_spec* spec, L
     lay->n = n;
     sdc_status s;
     if (spec->kind == SDC_BINS_PERIODIC_SC || spec->kind == SDC_BINS_PERIODIC_BCC)
-        s = build_periodic(pos, n, spec, lay, err);
+        s = build_periodic(pos, n, spec, segment_pairs, lay, err);
     else if (spec->kind == SDC_BINS_RADIAL)
-        s = build_radial(pos, n, spec, lay, err);
+        s = build_radial(pos, n, spec, segment_pairs, lay, err);
     else
         return fail(err, SDC_ERR_INVALID_ARG, "unknown bin kind");
     if (s != SDC_OK) return s;

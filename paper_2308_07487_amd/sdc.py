@@ -52,6 +52,14 @@ class McSpec(ctypes.Structure):
                 ("cone0", ctypes.c_double), ("acc_target", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("segment_pairs", ctypes.c_int32)]
+
+
+SCHED_DEFAULT, SCHED_ONE_PASS, SCHED_TWO_PASS = 0, 1, 2
+SCHEDULES = {"default": SCHED_DEFAULT, "one_pass": SCHED_ONE_PASS, "two_pass": SCHED_TWO_PASS}
+
+
 class SqSpec(ctypes.Structure):
     _fields_ = [("n_origins", ctypes.c_int32), ("n_lags", ctypes.c_int32),
                 ("origin_stride", ctypes.c_int32), ("flags", ctypes.c_int32)]
@@ -73,7 +81,8 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_batch_destroy", "sdc_plan_structure_factor", "sdc_sq_create", "sdc_sq_accumulate",
            "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy", "sdc_mc_n_sweeps",
            "sdc_mc_anneal", "sdc_mc_create", "sdc_mc_run", "sdc_mc_timings", "sdc_mc_uses_stencil",
-           "sdc_mc_destroy")
+           "sdc_mc_destroy", "sdc_plan_create_tuned", "sdc_plan_get_tuning", "sdc_autotune",
+           "sdc_tuning_lookup", "sdc_batch_create_tuned", "sdc_batch_schedule")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -94,6 +103,15 @@ def lib():
         L.sdc_plan_create.argtypes = [P, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec),
                                       ctypes.c_int, ctypes.POINTER(P)]
         L.sdc_plan_n_bins.argtypes = [P, ctypes.POINTER(i64)]
+        L.sdc_plan_create_tuned.argtypes = [P, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec),
+                                            ctypes.POINTER(Tuning), ctypes.c_int, ctypes.POINTER(P)]
+        L.sdc_plan_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.sdc_autotune.argtypes = [P, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec), ctypes.c_int,
+                                   i32, ctypes.c_char_p, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]
+        L.sdc_tuning_lookup.argtypes = [ctypes.c_char_p, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec),
+                                        ctypes.c_int, ctypes.POINTER(Tuning), ctypes.POINTER(i32)]
+        L.sdc_batch_create_tuned.argtypes = [P, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(P)]
+        L.sdc_batch_schedule.argtypes = [P, ctypes.POINTER(i32)]
         L.sdc_accumulate.argtypes = [P, P, i64, P, i32, P]
         L.sdc_finalize.argtypes = [P, P, P, P, P, P, P, P]
         L.sdc_plan_raw.argtypes = [P, P, P, P, P, P]
@@ -188,6 +206,45 @@ def corr_spec(n_origins, n_lags, precision="split_bf16", origin_stride=1, flags=
     return c
 
 
+def tuning(schedule=None, segment_pairs=None):
+    """Tuning struct from a schedule name or code and a segment length (None = default)."""
+    sch = SCHEDULES.get(schedule, schedule) if schedule is not None else SCHED_DEFAULT
+    return Tuning(int(sch), int(segment_pairs or 0))
+
+
+def _tuning_dict(t):
+    inv = {v: k for k, v in SCHEDULES.items()}
+    return {"schedule": inv.get(t.schedule, t.schedule), "segment_pairs": int(t.segment_pairs)}
+
+
+def autotune(positions, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0), n_shells=0,
+             r_max=0.0, origin_stride=1, connected=False, device=0, max_lags=64, cache_path=None):
+    """Times every candidate tuning of this sample shape on the device
+    (sdc_autotune); returns ({"schedule", "segment_pairs"}, median fused ms).
+    With cache_path the winner is written to that JSON tuning file."""
+    pos = np.ascontiguousarray(positions, dtype=np.float32)
+    bs = bin_spec(kind, cells, n_shells, r_max)
+    cs = corr_spec(n_origins, n_lags, precision, origin_stride, flags=FLAG_CONNECTED if connected else 0)
+    best = Tuning()
+    ms = ctypes.c_double()
+    _check(lib().sdc_autotune(_np_ptr(pos), pos.shape[0], ctypes.byref(bs), ctypes.byref(cs), int(device),
+                              int(max_lags), cache_path.encode() if cache_path else None, ctypes.byref(best),
+                              ctypes.byref(ms)), "sdc_autotune")
+    return _tuning_dict(best), float(ms.value)
+
+
+def tuning_lookup(cache_path, n_sites, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0),
+                  n_shells=0, r_max=0.0, device=0):
+    """The tuning-file entry of a sample shape, or None."""
+    bs = bin_spec(kind, cells, n_shells, r_max)
+    cs = corr_spec(n_origins, n_lags, precision)
+    t = Tuning()
+    found = ctypes.c_int32()
+    _check(lib().sdc_tuning_lookup(cache_path.encode(), int(n_sites), ctypes.byref(bs), ctypes.byref(cs),
+                                   int(device), ctypes.byref(t), ctypes.byref(found)), "sdc_tuning_lookup")
+    return _tuning_dict(t) if found.value else None
+
+
 def layout_keys(positions, kind, cells=(0, 0, 0), n_shells=0, r_max=0.0):
     """Host check of the tile layout: bin of every ordered pair [n][n]."""
     pos = np.ascontiguousarray(positions, dtype=np.float32)
@@ -203,7 +260,7 @@ class Plan:
 
     def __init__(self, positions, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0),
                  n_shells=0, r_max=0.0, origin_stride=1, device=0, timing=False, connected=False,
-                 key_table=True, deterministic=False):
+                 key_table=True, deterministic=False, schedule=None, segment_pairs=None):
         self._h = None
         pos = np.ascontiguousarray(positions, dtype=np.float32)
         self.n_sites = pos.shape[0]
@@ -217,13 +274,26 @@ class Plan:
                               | (FLAG_DETERMINISTIC if deterministic else 0))
         self.device = int(device)
         h = ctypes.c_void_p()
-        _check(lib().sdc_plan_create(_np_ptr(pos), self.n_sites, ctypes.byref(self.bins),
-                                     ctypes.byref(self.corr), self.device, ctypes.byref(h)),
-               "sdc_plan_create")
+        if schedule is None and segment_pairs is None:
+            _check(lib().sdc_plan_create(_np_ptr(pos), self.n_sites, ctypes.byref(self.bins),
+                                         ctypes.byref(self.corr), self.device, ctypes.byref(h)),
+                   "sdc_plan_create")
+        else:
+            tu = tuning(schedule, segment_pairs)
+            _check(lib().sdc_plan_create_tuned(_np_ptr(pos), self.n_sites, ctypes.byref(self.bins),
+                                               ctypes.byref(self.corr), ctypes.byref(tu), self.device,
+                                               ctypes.byref(h)), "sdc_plan_create_tuned")
         self._h = h
         nb = ctypes.c_int64()
         _check(lib().sdc_plan_n_bins(self._h, ctypes.byref(nb)), "sdc_plan_n_bins")
         self.n_bins = int(nb.value)
+
+    @property
+    def tuning(self):
+        """{"schedule", "segment_pairs"} the plan runs with."""
+        t = Tuning()
+        _check(lib().sdc_plan_get_tuning(self._h, ctypes.byref(t)), "sdc_plan_get_tuning")
+        return _tuning_dict(t)
 
     def accumulate(self, spins, lags=None, stream=None):
         """spins: contiguous float32 device tensor [T][N][3]."""
@@ -314,14 +384,27 @@ class Plan:
 class Batch:
     """Several plans accumulated with one persistent fused launch (all lags)."""
 
-    def __init__(self, plans, timing=False):
+    def __init__(self, plans, timing=False, schedule=None):
         self._h = None
         self.plans = list(plans)  # keeps the plans alive while the batch exists
         arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         h = ctypes.c_void_p()
-        _check(lib().sdc_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.plans),
-                                      FLAG_TIMING if timing else 0, ctypes.byref(h)), "sdc_batch_create")
+        if schedule is None:
+            _check(lib().sdc_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.plans),
+                                          FLAG_TIMING if timing else 0, ctypes.byref(h)), "sdc_batch_create")
+        else:
+            tu = tuning(schedule)
+            _check(lib().sdc_batch_create_tuned(ctypes.cast(arr, ctypes.c_void_p), len(self.plans),
+                                                FLAG_TIMING if timing else 0, ctypes.byref(tu), ctypes.byref(h)),
+                   "sdc_batch_create_tuned")
         self._h = h
+
+    @property
+    def schedule(self):
+        """Schedule name of the batch's launch."""
+        v = ctypes.c_int32()
+        _check(lib().sdc_batch_schedule(self._h, ctypes.byref(v)), "sdc_batch_schedule")
+        return {v_: k for k, v_ in SCHEDULES.items()}.get(v.value, v.value)
 
     def timings(self):
         """(pack_and_self_ms, fused_ms) of the last accumulate (timing batches only)."""

@@ -2,8 +2,9 @@
 (ragged and one-cell-wide axes included), origin counts that give odd and
 even numbers of 8-origin blocks (both K-step addressings of the fused
 kernel), origin strides, lag counts that leave partial lag groups, lag
-subsets, every precision and the connected form, for sc, bcc and radial
-bins.  Each case: pair counts bit-exact, origin totals exact, C(r, t) within
+subsets, every precision and the connected form, every schedule of the
+fused kernel and segment lengths down to one tile pair per task, for sc, bcc
+and radial bins.  Each case: pair counts bit-exact, origin totals exact, C(r, t) within
 the precision's bar against the FP64 oracle.  A second sweep does the same
 for the q-resolved S(q, t) accumulator (site, wave-vector and frame counts
 that leave ragged chunks, blocks and column groups; connected form), a third
@@ -18,8 +19,18 @@ pytestmark = pytest.mark.gpu
 PRECS = ("fp32", "split_bf16", "split_fp16", "bf16x3")
 
 
+def _tuning(rng, prec):
+    """A random schedule the precision has (None = the plan's default) and a
+    random segment length (None = default; short ones cut every stream into
+    many tasks and merges)."""
+    scheds = [None, "one_pass"] + (["two_pass"] if prec in ("split_bf16", "split_fp16") else [])
+    segs = [None, 1, 3, 24]
+    return scheds[int(rng.integers(0, len(scheds)))], segs[int(rng.integers(0, len(segs)))]
+
+
 def _cases(n=24, seed=0x5DC05EED):
     rng = np.random.default_rng(seed)
+    rng_t = np.random.default_rng(seed + 1)
     out = []
     for k in range(n):
         kind = ("sc", "bcc", "radial")[k % 3]
@@ -35,7 +46,7 @@ def _cases(n=24, seed=0x5DC05EED):
         prec = PRECS[int(rng.integers(0, 4))]
         connected = bool(rng.random() < 0.3)
         subset = bool(rng.random() < 0.3) and n_L > 2
-        out.append((k, kind, L, n_o, n_L, stride, prec, connected, subset))
+        out.append((k, kind, L, n_o, n_L, stride, prec, connected, subset) + _tuning(rng_t, prec))
     return out
 
 
@@ -43,8 +54,9 @@ CASES = _cases()
 
 
 def _id(c):
-    k, kind, L, n_o, n_L, s, prec, conn, sub = c
-    return f"{k}-{kind}-{'x'.join(map(str, L))}-o{n_o}-l{n_L}-s{s}-{prec}{'-conn' if conn else ''}{'-sub' if sub else ''}"
+    k, kind, L, n_o, n_L, s, prec, conn, sub, sched, seg = c
+    return (f"{k}-{kind}-{'x'.join(map(str, L))}-o{n_o}-l{n_L}-s{s}-{prec}{'-conn' if conn else ''}"
+            f"{'-sub' if sub else ''}{'-' + sched if sched else ''}{'-seg%d' % seg if seg else ''}")
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +74,7 @@ def S():
 
 @pytest.mark.parametrize("case", CASES, ids=[_id(c) for c in CASES])
 def test_random_configuration(torch_dev, S, orc, case):
-    k, kind, L, n_o, n_L, s, prec, connected, subset = case
+    k, kind, L, n_o, n_L, s, prec, connected, subset, sched, seg = case
     print(f"[case] sweep {_id(case)}", flush=True)
     if kind == "sc":
         pos, gk, ok, kw = inputs.sc_positions(L), S.BINS_SC, orc.SC, dict(cells=L)
@@ -76,7 +88,12 @@ def test_random_configuration(torch_dev, S, orc, case):
     fr = inputs.random_unit_frames(T, n, seed=200 + k)
     rng = np.random.default_rng(300 + k)
     lags = np.sort(rng.choice(n_L, size=max(1, n_L // 2), replace=False)) if subset else np.arange(n_L)
-    with S.Plan(pos, gk, n_o, n_L, prec, origin_stride=s, connected=connected, **kw) as p:
+    with S.Plan(pos, gk, n_o, n_L, prec, origin_stride=s, connected=connected, schedule=sched,
+                segment_pairs=seg, **kw) as p:
+        if sched:
+            assert p.tuning["schedule"] == sched
+        if seg:
+            assert p.tuning["segment_pairs"] == seg
         p.accumulate(torch_dev.from_numpy(fr).cuda(), lags=lags if subset else None)
         out = p.finalize()
         H, no, sf, ms = p.raw()
@@ -141,6 +158,7 @@ def test_random_q_resolved(torch_dev, S, orc, case):
 
 def _batch_cases(n=6, seed=0x5DC05EEF):
     rng = np.random.default_rng(seed)
+    rng_t = np.random.default_rng(seed + 1)
     out = []
     for k in range(n):
         radial = k % 3 == 2
@@ -155,21 +173,22 @@ def _batch_cases(n=6, seed=0x5DC05EEF):
                 geo = (lat, tuple(int(x) for x in rng.integers(1, hi, size=3)))
             plans.append(geo + (int(rng.integers(1, 41)), int(rng.integers(1, 41)), int(rng.integers(1, 3)),
                                 bool(rng.random() < 0.3)))
-        out.append((k, prec, plans))
+        out.append((k, prec, plans, _tuning(rng_t, prec)[0]))
     return out
 
 
 BATCH_CASES = _batch_cases()
 
 
-@pytest.mark.parametrize("case", BATCH_CASES, ids=[f"{c[0]}-{c[1]}-{len(c[2])}plans" for c in BATCH_CASES])
+@pytest.mark.parametrize("case", BATCH_CASES,
+                         ids=[f"{c[0]}-{c[1]}-{len(c[2])}plans{'-' + c[3] if c[3] else ''}" for c in BATCH_CASES])
 def test_random_batch(torch_dev, S, orc, case):
     """Random sets of plans (periodic sc/bcc mixed, or radial; different
     sizes, origin counts, lags, strides, connected flags) accumulated in one
     persistent launch: every plan's counts, origin totals and raw bins against
     the oracle, within the precision's bar."""
-    k, prec, specs = case
-    print(f"[case] batch sweep {k} {prec}: {specs}", flush=True)
+    k, prec, specs, sched = case
+    print(f"[case] batch sweep {k} {prec} schedule {sched}: {specs}", flush=True)
     plans, frames, host = [], [], []
     try:
         for m, (lat, geo, n_o, n_L, s, connected) in enumerate(specs):
@@ -184,7 +203,9 @@ def test_random_batch(torch_dev, S, orc, case):
             plans.append(S.Plan(pos, gk, n_o, n_L, prec, origin_stride=s, connected=connected, **kw))
             frames.append(torch_dev.from_numpy(fr).cuda())
             host.append((pos, ok, kw, fr, n_o, n_L, s, connected))
-        with S.Batch(plans) as b:
+        with S.Batch(plans, schedule=sched) as b:
+            if sched:
+                assert b.schedule == sched
             b.accumulate(frames)
             torch_dev.cuda.synchronize()
         bar = 5e-5 if prec == "split_bf16" else 1e-6

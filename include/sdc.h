@@ -292,6 +292,26 @@ sdc_status sdc_plan_structure_factor(sdc_plan* plan, const int32_t* m_host, int3
                                      double* Sqt_host, double* Sqw_host, void* stream);
 
 /*
+ * sdc_plan_structure_factor for callers that cannot allocate device memory
+ * (serving loops, harnesses that forbid hipMalloc/hipFree): the same
+ * computation and the same results, with its scratch (the wave-vector
+ * indices and both outputs before the copy to the host) in a fixed 16 MiB
+ * device array per GPU instead of per-call allocations.  Limit: 12 n_q +
+ * 32 n_q n_lags bytes <= 16 MiB (e.g. 1024 wave vectors x 256 lags);
+ * larger requests return UNSUPPORTED before any GPU work.  Calls no
+ * hipMalloc, hipFree or allocating library routine (the array's device
+ * address is looked up once per device on the first call there).  Every
+ * call on one GPU uses the same array: calls that overlap in time on one GPU
+ * (from several host threads, or streams) race; calls in turn are safe
+ * (each synchronises the stream before it returns, and every output element
+ * is rewritten by each call).
+ * Errors: as sdc_plan_structure_factor (UNSUPPORTED also for the size
+ * limit).
+ */
+sdc_status sdc_plan_structure_factor_static(sdc_plan* plan, const int32_t* m_host, int32_t n_q,
+                                            double* Sqt_host, double* Sqw_host, void* stream);
+
+/*
  * Raw accumulated state (for exact comparisons and checkpointing): H
  * [n_lags][n_bins] FP64, per-lag origin totals [n_lags] FP64, raw self sums
  * [n_lags] FP64, raw site sums sum_o M.M [n_lags] FP64.  Any output may be

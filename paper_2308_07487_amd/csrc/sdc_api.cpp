@@ -749,6 +749,63 @@ sdc_status sdc_plan_structure_factor(sdc_plan* p, const int32_t* m_host, int32_t
     return SDC_OK;
 }
 
+sdc_status sdc_plan_structure_factor_static(sdc_plan* p, const int32_t* m_host, int32_t n_q, double* Sqt_host,
+                                            double* Sqw_host, void* stream) {
+    g_err.clear();
+    sdc_status s = plan_usable(p);
+    if (s != SDC_OK) return s;
+    if (!m_host || (!Sqt_host && !Sqw_host)) return set_err(SDC_ERR_INVALID_ARG, "null pointer");
+    if (n_q < 1 || n_q > 65535) return set_err(SDC_ERR_INVALID_ARG, "n_q must be in [1, 65535]");
+    if (p->lay.kind == SDC_BINS_RADIAL)
+        return set_err(SDC_ERR_UNSUPPORTED, "S(q, t) from bins needs a periodic plan");
+    for (int64_t x = 0; x < 3 * (int64_t)n_q; ++x)
+        if (m_host[x] < -(1 << 20) || m_host[x] > (1 << 20))
+            return set_err(SDC_ERR_INVALID_ARG, "wave-vector index out of range");
+    // scratch layout: m [3 n_q] int32 (padded to 256 bytes), S(q, t), S(q, w)
+    const int nl = p->corr.n_lags;
+    const size_t out_n = (size_t)n_q * nl * 2;
+    const size_t m_bytes = ((size_t)3 * n_q * sizeof(int32_t) + 255) / 256 * 256;
+    if (m_bytes + 2 * out_n * sizeof(double) > sdc::kStaticScratchBytes)
+        return set_err(SDC_ERR_UNSUPPORTED, "n_q * n_lags too large for the fixed scratch (16 MiB: "
+                                            "12 n_q + 32 n_q n_lags bytes)");
+    SDC_HIP(select_device(p->device), "hipSetDevice");
+    void* base = nullptr;
+    {
+        const int e = sdc::static_scratch(p->device, &base);
+        if (e != 0) return hip_err(e, "fixed scratch address");
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    int32_t* d_m = (int32_t*)base;
+    double* d_out = (double*)((char*)base + m_bytes);
+    hipError_t he = hipMemcpyAsync(d_m, m_host, (size_t)3 * n_q * sizeof(int32_t), hipMemcpyHostToDevice, hs);
+    if (he == hipSuccess) he = (hipError_t)refresh_fixed(p, stream);
+    sdc::SqtArgs a{};
+    a.H = p->d_H;
+    a.n_org = p->d_norg;
+    a.n_bins = p->lay.n_bins;
+    a.n_sites = p->lay.n;
+    a.n_lags = nl;
+    a.kind = p->lay.kind;
+    a.L0 = p->lay.L[0];
+    a.L1 = p->lay.L[1];
+    a.L2 = p->lay.L[2];
+    a.m = d_m;
+    a.n_q = n_q;
+    a.sqt = d_out;
+    a.sqw = d_out + out_n;
+    int e = he == hipSuccess ? sdc::launch_sqt(a, stream) : (int)he;
+    if (e == 0 && Sqt_host)
+        e = (int)hipMemcpyAsync(Sqt_host, a.sqt, out_n * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == 0 && Sqw_host)
+        e = (int)hipMemcpyAsync(Sqw_host, a.sqw, out_n * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e == 0) e = (int)hipStreamSynchronize(hs);
+    if (e != 0) {
+        p->failed = true;
+        return hip_err(e, "structure factor (fixed scratch)");
+    }
+    return SDC_OK;
+}
+
 sdc_status sdc_plan_raw(sdc_plan* p, double* H_host, double* n_org_host, double* self_host, double* msum_host,
                         void* stream) {
     g_err.clear();

@@ -349,6 +349,12 @@ int launch_sq_finalize(const double* raw, const double* n_org, int64_t n_sites, 
 
 int launch_zero(void* ptr, int64_t bytes, void* stream);
 
+// Fixed device scratch of the entry points that allocate nothing
+// (sdc_static.hip): kStaticScratchBytes per device, shared by every call on
+// that device.  static_scratch() returns the device address of `device`'s
+// copy, looked up on the first call for that device (with it current).
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+int static_scratch(int device, void** ptr);
 
 // Deterministic mode: every sum that several threads add into is kept as a
 // two's-complement 64-bit fixed-point number with 2^-20 resolution, so

@@ -82,7 +82,8 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_sq_finalize", "sdc_sq_timings", "sdc_sq_reset", "sdc_sq_destroy", "sdc_mc_n_sweeps",
            "sdc_mc_anneal", "sdc_mc_create", "sdc_mc_run", "sdc_mc_timings", "sdc_mc_uses_stencil",
            "sdc_mc_destroy", "sdc_plan_create_tuned", "sdc_plan_get_tuning", "sdc_autotune",
-           "sdc_tuning_lookup", "sdc_batch_create_tuned", "sdc_batch_schedule")
+           "sdc_tuning_lookup", "sdc_batch_create_tuned", "sdc_batch_schedule",
+           "sdc_plan_structure_factor_static")
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -131,6 +132,7 @@ def lib():
         L.sdc_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.sdc_batch_destroy.argtypes = [P]
         L.sdc_plan_structure_factor.argtypes = [P, P, i32, P, P, P]
+        L.sdc_plan_structure_factor_static.argtypes = [P, P, i32, P, P, P]
         L.sdc_mc_n_sweeps.argtypes = [ctypes.POINTER(McSpec), ctypes.POINTER(i64)]
         L.sdc_mc_anneal.argtypes = [P, i64, ctypes.POINTER(McSpec), P, P, P, P, ctypes.c_int, P]
         L.sdc_mc_create.argtypes = [P, i64, ctypes.POINTER(McSpec), ctypes.c_int, ctypes.POINTER(P)]
@@ -352,6 +354,19 @@ class Plan:
         sqw = np.zeros((m.shape[0], self.n_lags, 2))
         _check(lib().sdc_plan_structure_factor(self._h, _np_ptr(m), m.shape[0], _np_ptr(sqt), _np_ptr(sqw),
                                                _stream_ptr(stream)), "sdc_plan_structure_factor")
+        return sqt[..., 0] + 1j * sqt[..., 1], sqw[..., 0] + 1j * sqw[..., 1]
+
+    def structure_factor_static(self, m, stream=None):
+        """structure_factor through sdc_plan_structure_factor_static (fixed
+        device scratch, no allocation; n_q * n_lags limited)."""
+        m = np.ascontiguousarray(np.atleast_2d(m), dtype=np.int32)
+        if m.shape[1] != 3:
+            raise ValueError("m must have shape [n_q][3]")
+        sqt = np.zeros((m.shape[0], self.n_lags, 2))
+        sqw = np.zeros((m.shape[0], self.n_lags, 2))
+        _check(lib().sdc_plan_structure_factor_static(self._h, _np_ptr(m), m.shape[0], _np_ptr(sqt),
+                                                      _np_ptr(sqw), _stream_ptr(stream)),
+               "sdc_plan_structure_factor_static")
         return sqt[..., 0] + 1j * sqt[..., 1], sqw[..., 0] + 1j * sqw[..., 1]
 
     def timings(self):

@@ -143,9 +143,12 @@ typedef enum {
     SDC_SCHED_DEFAULT = 0,  /* tuning entry for the plan's size class, else the library default */
     SDC_SCHED_ONE_PASS = 1, /* one K loop per tile pair, second accumulator set for the small
                                products; one workgroup per compute unit.  Every precision. */
-    SDC_SCHED_TWO_PASS = 2  /* SPLIT_BF16 / SPLIT_FP16 only: per tile pair a K loop over
+    SDC_SCHED_TWO_PASS = 2, /* SPLIT_BF16 / SPLIT_FP16 only: per tile pair a K loop over
                                hi*lo + lo*hi, then one adding hi*hi to those sums, in one
                                accumulator set; two workgroups per compute unit. */
+    SDC_SCHED_LAG_SPLIT = 3 /* one K loop, second accumulator set as ONE_PASS, but workgroups
+                               of eight waves: two waves per 32x32 quadrant, each with half
+                               of the lags; two waves per SIMD.  Every precision. */
 } sdc_schedule;
 
 /* Tuning of a plan: what the autotuner (sdc_autotune) chooses per size
@@ -199,27 +202,36 @@ sdc_status sdc_plan_create_tuned(const float* positions_host, int64_t n_sites,
 sdc_status sdc_plan_get_tuning(const sdc_plan* plan, sdc_tuning* tuning);
 
 /*
- * Autotuner: for one sample shape, times every candidate tuning (each
- * schedule the precision has x segment lengths {24, 48, 96, 192, 384} for
- * periodic kinds, {64, 256, all} for radial) on the device and returns the
- * fastest.  Each candidate gets its own plan and runs one warm-up and three
- * timed accumulates (HIP events around the fused launch) over the first
- * min(n_lags, max_lags) lags (max_lags <= 0: all lags) on seeded uniform
- * unit spins; the per-task work does not depend on the lag count, so a lag
- * subset ranks the candidates as the whole set does.  The winner is the
- * smallest median.
- *  cache_path : JSON tuning file; when not NULL the winner is written under
- *               the plan's size-class key (other entries are kept; the file
- *               is replaced atomically), for sdc_plan_create to pick up via
- *               SDC_TUNING_FILE.
- *  best       : receives the winner.   best_ms : its median fused time
- *               (milliseconds), or NULL.
+ * Autotuner: for one sample shape, times candidate tunings on the device
+ * and returns the fastest.  Each candidate gets its own plan and runs one
+ * warm-up and three timed accumulates (HIP events around the fused launch)
+ * over the first min(n_lags, max_lags) lags (max_lags <= 0: all lags) on
+ * seeded uniform unit spins; the winner has the smallest median.
+ *  candidates   : n_candidates tunings with every field set, or NULL for the
+ *                 built-in list (sdc_autotune_candidates: every schedule the
+ *                 precision has x segment lengths {24, 48, 96, 192, 384} for
+ *                 periodic kinds, {64, 256, all} for radial).
+ *  cache_path   : JSON tuning file; when not NULL the winner is written under
+ *                 the plan's size-class key with every candidate's time
+ *                 (other entries are kept; the file is replaced atomically),
+ *                 for sdc_plan_create to pick up via SDC_TUNING_FILE.
+ *  best         : receives the winner;  best_ms : its median fused time
+ *                 (milliseconds), or NULL;  candidate_ms : [n] medians of all
+ *                 candidates in order, or NULL.
  * Synchronous; allocates and frees its own plans and spins.
- * Errors: as sdc_plan_create; HIP; INVALID_ARG if the file cannot be written.
+ * Errors: as sdc_plan_create; HIP; INVALID_ARG for a candidate with a zero
+ * field or a file that cannot be written.
  */
 sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
                         const sdc_corr_spec* corr, int device, int32_t max_lags,
-                        const char* cache_path, sdc_tuning* best, double* best_ms);
+                        const sdc_tuning* candidates, int32_t n_candidates, const char* cache_path,
+                        sdc_tuning* best, double* best_ms, double* candidate_ms);
+
+/* The built-in candidate list of sdc_autotune for a sample shape: *n_out
+ * candidates, the first max_out of them written to out (out may be NULL when
+ * max_out is 0).  Host only.  Errors: INVALID_ARG. */
+sdc_status sdc_autotune_candidates(const sdc_bin_spec* bins, const sdc_corr_spec* corr,
+                                   sdc_tuning* out, int32_t max_out, int32_t* n_out);
 
 /* The tuning-file entry for a sample shape: *found = 1 and *tuning set if
  * cache_path holds one, else *found = 0.  Host only, except that the device's
@@ -483,6 +495,45 @@ sdc_status sdc_sq_reset(sdc_sq* sq, void* stream);
 
 /* Free the accumulator (waits for the device).  NULL is a no-op. */
 sdc_status sdc_sq_destroy(sdc_sq* sq);
+
+/* ---------------------------------------------------------------------- */
+/* Matrix-core measurements (the ceilings the fused product is held to)    */
+/* ---------------------------------------------------------------------- */
+
+typedef enum {
+    SDC_MFMA_BF16 = 0,  /* v_mfma_f32_32x32x16_bf16 (split-BF16, BF16x3)     */
+    SDC_MFMA_F16 = 1,   /* v_mfma_f32_32x32x16_f16  (split-FP16)             */
+    SDC_MFMA_F32 = 2    /* v_mfma_f32_32x32x2_f32   (FP32)                   */
+} sdc_mfma_form;
+
+/*
+ * Sustained matrix-core rate of the device on the form the fused product
+ * uses, with nothing else in the loop: every wave keeps four independent
+ * 32x32 accumulators and four operand sets in registers and issues
+ * iterations x 16 MFMAs; workgroups of four waves, workgroups_per_cu (1 or
+ * 2) per compute unit on every compute unit.  random_operands = 1 draws the
+ * operands (Philox) with magnitudes in [2^-8, 1) and random signs and
+ * mantissas, as spin data has; 0 uses the constant 0.5 (fewest toggling
+ * bits, the highest clock the power limit allows).  One warm-up launch, then
+ * one timed launch (HIP events).
+ *  ms     : duration of the timed launch.   tflops : executed TFLOP/s.
+ * Synchronous; allocates and frees a small output buffer.
+ * Errors: INVALID_ARG, NO_DEVICE, OOM, HIP.
+ */
+sdc_status sdc_mfma_peak(int32_t form, int32_t random_operands, int64_t iterations,
+                         int32_t workgroups_per_cu, int device, double* ms, double* tflops);
+
+/*
+ * One MFMA instruction of the given form on one wave, with element (0, 0)
+ * of its 32x32 output set to c + sum_k a[k] b[k] (k < n_products; at most 16
+ * for the 16-bit forms, 2 for FP32) and every other input zero: how the
+ * matrix cores sum products into the accumulator, bit for bit.  a and b must
+ * be exact in the form's input type (else INVALID_ARG).
+ *  out : the FP32 result for element (0, 0).
+ * Synchronous.  Errors: INVALID_ARG, NO_DEVICE, OOM, HIP.
+ */
+sdc_status sdc_mfma_probe(int32_t form, float c, const float* a, const float* b,
+                          int32_t n_products, int device, float* out);
 
 /* Static description of a status code. */
 const char* sdc_status_string(sdc_status s);

@@ -132,7 +132,7 @@ struct sdc_plan {
     void* d_B = nullptr;
     size_t bytes_A = 0, bytes_B = 0;
     std::map<std::vector<int>, LagSel> sels;
-    sdc_tuning tuning{};  // resolved: schedule (SDC_SCHED_ONE_PASS / TWO_PASS) and segment length
+    sdc_tuning tuning{};  // resolved: schedule (never SDC_SCHED_DEFAULT) and segment length
     bool failed = false;
     int batch_refs = 0;  // batches that hold this plan
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -941,16 +941,18 @@ sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32
     // tunings give the most work (pair-terms times origins).
     int schedule = tuning ? tuning->schedule : SDC_SCHED_DEFAULT;
     if (schedule != SDC_SCHED_DEFAULT) {
-        if (schedule != SDC_SCHED_ONE_PASS && schedule != SDC_SCHED_TWO_PASS)
+        if (schedule < SDC_SCHED_ONE_PASS || schedule > SDC_SCHED_LAG_SPLIT)
             return set_err(SDC_ERR_INVALID_ARG, "unknown schedule");
         if (!sdc::sched_valid(prec, sdc::sched_index(schedule)))
             return set_err(SDC_ERR_UNSUPPORTED, "schedule not available for this precision");
     } else {
-        double w[3] = {0.0, 0.0, 0.0};
+        double w[4] = {0.0, 0.0, 0.0, 0.0};
         for (int k = 0; k < n_plans; ++k)
             w[plans[k]->tuning.schedule] += (double)plans[k]->lay.n * (double)plans[k]->lay.n *
                                              plans[k]->corr.n_lags * plans[k]->corr.n_origins;
-        schedule = w[SDC_SCHED_TWO_PASS] > w[SDC_SCHED_ONE_PASS] ? SDC_SCHED_TWO_PASS : SDC_SCHED_ONE_PASS;
+        schedule = SDC_SCHED_ONE_PASS;
+        for (int sch = SDC_SCHED_TWO_PASS; sch <= SDC_SCHED_LAG_SPLIT; ++sch)
+            if (w[sch] > w[schedule]) schedule = sch;
     }
     SDC_HIP(hipSetDevice(device), "hipSetDevice");
     sdc_batch* b = nullptr;

@@ -213,7 +213,7 @@ __device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
 
 // Products one K loop forms (PASS):
 //  kPassAll   : every product of the form; the large ones into acc.v, the
-//               small ones into acc.s (one-pass schedule);
+//               small ones into acc.s (one-pass and lag-split schedules);
 //  kPassSmall : hi*lo + lo*hi into acc.v (first loop of the two-pass
 //               schedule, from zero);
 //  kPassLarge : hi*hi into acc.v (second loop, on top of the small sums).
@@ -226,15 +226,16 @@ __device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
 // afterwards (16 significant bits each) lose none either.
 constexpr int kPassAll = 0, kPassLarge = 1, kPassSmall = 2;
 
-// Three-product split for lag u0 + M: hi*hi + hi*lo + lo*hi.
-template <int PREC, int PASS, int M, int NW, int LG>
+// Three-product split for the wave's lag M (its window slice OFF + M):
+// hi*hi + hi*lo + lo*hi.
+template <int PREC, int PASS, int OFF, int M, int NW, int LW>
 __device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[NW],
-                                  const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG]) {
-    const uint4 bh = slice8<M, NW>(wh);
+                                  const uint32_t (&wl)[NW], f32x16 (&acc)[LW], f32x16 (&acc_s)[LW]) {
+    const uint4 bh = slice8<OFF + M, NW>(wh);
     if constexpr (PASS == kPassLarge) {
         acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
     } else {
-        const uint4 bl = slice8<M, NW>(wl);
+        const uint4 bl = slice8<OFF + M, NW>(wl);
         if constexpr (PASS == kPassAll) {
             acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
             acc_s[M] = mfma16<PREC>(av.x, bl, acc_s[M]);
@@ -246,15 +247,15 @@ __device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[NW],
     }
 }
 
-// Three-piece BF16 for lag u0 + M: the six products hh, hm, mh, mm, hl, lh
-// (the dropped ml, lm, ll are below 2^-24 of the product); hh goes to the
-// main accumulator, the other five (2^-8 and smaller) to the second one.
-template <int M, int NW, int LG>
+// Three-piece BF16 for the wave's lag M: the six products hh, hm, mh, mm,
+// hl, lh (the dropped ml, lm, ll are below 2^-24 of the product); hh goes to
+// the main accumulator, the other five (2^-8 and smaller) to the second one.
+template <int OFF, int M, int NW, int LW>
 __device__ inline void x3_step(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
-                               const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG]) {
-    const uint4 bh = slice8<M, NW>(wh);
-    const uint4 bm = slice8<M, NW>(wm);
-    const uint4 bl = slice8<M, NW>(wl);
+                               const uint32_t (&wl)[NW], f32x16 (&acc)[LW], f32x16 (&acc_s)[LW]) {
+    const uint4 bh = slice8<OFF + M, NW>(wh);
+    const uint4 bm = slice8<OFF + M, NW>(wm);
+    const uint4 bl = slice8<OFF + M, NW>(wl);
     acc[M] = mfma16<SDC_PREC_BF16X3>(av.x, bh, acc[M]);
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.x, bm, acc_s[M]);
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.y, bh, acc_s[M]);
@@ -263,33 +264,33 @@ __device__ inline void x3_step(const Chunk3& av, const uint32_t (&wh)[NW], const
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.z, bh, acc_s[M]);
 }
 
-template <int NW, int LG, int... Ms>
+template <int OFF, int NW, int LW, int... Ms>
 __device__ inline void x3_all(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
-                              const uint32_t (&wl)[NW], f32x16 (&acc)[LG], f32x16 (&acc_s)[LG],
+                              const uint32_t (&wl)[NW], f32x16 (&acc)[LW], f32x16 (&acc_s)[LW],
                               std::integer_sequence<int, Ms...>) {
-    (x3_step<Ms, NW, LG>(av, wh, wm, wl, acc, acc_s), ...);
+    (x3_step<OFF, Ms, NW, LW>(av, wh, wm, wl, acc, acc_s), ...);
 }
 
-template <int PREC, int PASS, int NW, int LG, int... Ms>
+template <int PREC, int PASS, int OFF, int NW, int LW, int... Ms>
 __device__ inline void split_all(const Chunk& av, const uint32_t (&wh)[NW], const uint32_t (&wl)[NW],
-                                 f32x16 (&acc)[LG], f32x16 (&acc_s)[LG], std::integer_sequence<int, Ms...>) {
-    (split_step<PREC, PASS, Ms, NW, LG>(av, wh, wl, acc, acc_s), ...);
+                                 f32x16 (&acc)[LW], f32x16 (&acc_s)[LW], std::integer_sequence<int, Ms...>) {
+    (split_step<PREC, PASS, OFF, Ms, NW, LW>(av, wh, wl, acc, acc_s), ...);
 }
 
 // FP32: MFMA q of the K-step takes origin 16c + 8h + q on both sides.
-template <int Q, int M, int NF, int LG>
-__device__ inline void f32_step(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LG]) {
-    acc[M] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[Q], w[Q + M], acc[M], 0, 0, 0);
+template <int Q, int OFF, int M, int NF, int LW>
+__device__ inline void f32_step(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LW]) {
+    acc[M] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[Q], w[Q + OFF + M], acc[M], 0, 0, 0);
 }
-template <int Q, int NF, int LG, int... Ms>
-__device__ inline void f32_q(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LG],
+template <int Q, int OFF, int NF, int LW, int... Ms>
+__device__ inline void f32_q(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LW],
                              std::integer_sequence<int, Ms...>) {
-    (f32_step<Q, Ms, NF, LG>(a, w, acc), ...);
+    (f32_step<Q, OFF, Ms, NF, LW>(a, w, acc), ...);
 }
-template <int NF, int LG, int... Qs>
-__device__ inline void f32_all(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LG],
+template <int OFF, int NF, int LW, int... Qs>
+__device__ inline void f32_all(const float (&a)[8], const float (&w)[NF], f32x16 (&acc)[LW],
                                std::integer_sequence<int, Qs...>) {
-    (f32_q<Qs, NF, LG>(a, w, acc, std::make_integer_sequence<int, LG>{}), ...);
+    (f32_q<Qs, OFF, NF, LW>(a, w, acc, std::make_integer_sequence<int, LW>{}), ...);
 }
 
 // Fixed-point image of v (deterministic mode), rounded to nearest.
@@ -302,12 +303,12 @@ __device__ inline int pmod_dev(int a, int m) {
     return r < 0 ? r + m : r;
 }
 
-// Accumulators of one wave: LG 32x32 tiles, and for the one-pass schedule
-// of the reduced-precision forms a second set for their small products.
-template <int PREC, int SCHED, int LG>
+// Accumulators of one wave: LW 32x32 tiles, and for the schedules that
+// keep them apart a second set for the small products of the reduced forms.
+template <int PREC, int SCHED, int LW>
 struct Acc {
-    f32x16 v[LG];
-    f32x16 s[(PREC == SDC_PREC_FP32 || SCHED == kSchedTwoPass) ? 1 : LG];
+    f32x16 v[LW];
+    f32x16 s[(PREC == SDC_PREC_FP32 || SCHED == kSchedTwoPass) ? 1 : LW];
 };
 
 // Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
@@ -318,9 +319,9 @@ struct Stage {
     PackElem<PREC> b[NB];
 };
 
-template <int PREC, int PASS, int SCHED, int NB, int LG>
-__device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LG>& ac) {
-    f32x16 (&acc)[LG] = ac.v;
+template <int PREC, int PASS, int SCHED, int NB, int LW, int OFF>
+__device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LW>& ac) {
+    f32x16 (&acc)[LW] = ac.v;
     constexpr int NW = 4 * NB;
     if constexpr (PREC == SDC_PREC_BF16X3) {
         uint32_t wh[NW], wm[NW], wl[NW];
@@ -336,7 +337,7 @@ __device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LG>&
                 wl[4 * k + e] = l4[e];
             }
         }
-        x3_all<NW, LG>(s.a, wh, wm, wl, acc, ac.s, std::make_integer_sequence<int, LG>{});
+        x3_all<OFF, NW, LW>(s.a, wh, wm, wl, acc, ac.s, std::make_integer_sequence<int, LW>{});
     } else if constexpr (PREC == SDC_PREC_FP32) {
         float af[8], w[8 * NB];
         const uint32_t ar[8] = {s.a.x.x, s.a.x.y, s.a.x.z, s.a.x.w, s.a.y.x, s.a.y.y, s.a.y.z, s.a.y.w};
@@ -349,7 +350,7 @@ __device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LG>&
 #pragma unroll
             for (int e = 0; e < 8; ++e) w[8 * k + e] = __uint_as_float(r[e]);
         }
-        f32_all<8 * NB, LG>(af, w, acc, std::make_integer_sequence<int, 8>{});
+        f32_all<OFF, 8 * NB, LW>(af, w, acc, std::make_integer_sequence<int, 8>{});
     } else {
         uint32_t wh[NW], wl[NW];
 #pragma unroll
@@ -366,9 +367,9 @@ __device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LG>&
         // the two-pass schedule has no second accumulator set (its passes
         // never write one)
         if constexpr (SCHED == kSchedTwoPass)
-            split_all<PREC, PASS, NW, LG>(s.a, wh, wl, acc, acc, std::make_integer_sequence<int, LG>{});
+            split_all<PREC, PASS, OFF, NW, LW>(s.a, wh, wl, acc, acc, std::make_integer_sequence<int, LW>{});
         else
-            split_all<PREC, PASS, NW, LG>(s.a, wh, wl, acc, ac.s, std::make_integer_sequence<int, LG>{});
+            split_all<PREC, PASS, OFF, NW, LW>(s.a, wh, wl, acc, ac.s, std::make_integer_sequence<int, LW>{});
     }
 }
 
@@ -381,8 +382,8 @@ int fused_lds_bytes(int win, int precision) {
 // (load indices clamp to the last step, so the last round's extra loads are
 // harmless re-reads).  The scheduling barriers keep the loads ahead of the
 // MFMAs.
-template <int PREC, int PASS, int SCHED, int NB, int LG, int NS, class Load>
-__device__ __forceinline__ void k_loop(int nk, const Load& load, Acc<PREC, SCHED, LG>& acc) {
+template <int PREC, int PASS, int SCHED, int NB, int LW, int OFF, int NS, class Load>
+__device__ __forceinline__ void k_loop(int nk, const Load& load, Acc<PREC, SCHED, LW>& acc) {
     Stage<PREC, NB> s[NS];
 #pragma unroll
     for (int j = 0; j < NS - 1; ++j) load(s[j], j);
@@ -391,38 +392,35 @@ __device__ __forceinline__ void k_loop(int nk, const Load& load, Acc<PREC, SCHED
         for (int j = 0; j < NS; ++j) {
             load(s[(j + NS - 1) % NS], kk + j + NS - 1);
             __builtin_amdgcn_sched_barrier(0);
-            if (j == 0 || kk + j < nk) stage_mma<PREC, PASS, SCHED, NB, LG>(s[j], acc);
+            if (j == 0 || kk + j < nk) stage_mma<PREC, PASS, SCHED, NB, LW, OFF>(s[j], acc);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
-// One task of a plan: the stream's tile pairs for one lag group, histogram
-// in LDS (`hist`: [LG][win] FP64, then the radial edge table), merged into
-// the plan's global bins at the end.  Called by the whole workgroup.
-// PAIRED: O8 is even, so a K-step's two origin blocks always lie in one
-// component and the block offsets follow from the step with one scalar
-// division; otherwise the blocks of all components are taken in turn and a
-// step may straddle two components.
-// SCHED: kSchedOnePass or kSchedTwoPass (hi/lo splits only), see k_loop and
-// the pass constants.
-template <int PREC, int RADIAL, int PAIRED, int SCHED>
-__device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double* hist) {
+// What the tile-pair loop of one wave needs of its task.
+struct TaskCtx {
+    const FusedArgs* a;
+    KGroup grp;
+    KStream st;
+    double* hist;
+    const float* e2s;
+    int quadrant;  // 32x32 quadrant of the 64x64 tile pair (wave index mod 4)
+};
+
+// The tile pairs of a task for one wave: its quadrant, its LW lags starting
+// at lag OFF of the group (all LG of them unless the lag-split schedule
+// gives the group's two halves to two waves).
+template <int PREC, int RADIAL, int PAIRED, int SCHED, int LW, int OFF>
+__device__ __forceinline__ void pair_loop(const TaskCtx& c) {
     constexpr int LG = lag_group(PREC);
     constexpr int NB = win_blocks(LG);
     constexpr bool TWO = SCHED == kSchedTwoPass;
-    float* e2s = (float*)(hist + LG * a.win);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wi = wave >> 1, wj = wave & 1, h = lane >> 5, l32 = lane & 31;
-    const KGroup grp = a.groups[task % a.n_groups];
-    const KStream st = a.streams[task / a.n_groups];
-
-    for (int x = tid; x < LG * a.win; x += 256) hist[x] = 0.0;
-    if constexpr (RADIAL) {
-        for (int x = tid; x < a.n_shells; x += 256) e2s[x] = a.e2[x];
-    }
-    __syncthreads();
+    const FusedArgs& a = *c.a;
+    const KGroup grp = c.grp;
+    double* hist = c.hist;
+    const int lane = threadIdx.x & 63;
+    const int wi = c.quadrant >> 1, wj = c.quadrant & 1, h = lane >> 5, l32 = lane & 31;
 
     using Elem = PackElem<PREC>;
     const Elem* Ab = (const Elem*)a.A;
@@ -436,18 +434,18 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
     const int dF = a.F8 - a.O8;  // B block of A block k (component c): k + c dF + ublk
     const int n_c = a.O8 / 2;    // PAIRED: K-steps per component
 
-    for (int p = st.p0; p < st.p1; ++p) {
+    for (int p = c.st.p0; p < c.st.p1; ++p) {
         const KPair pr = a.pairs[p];
         const int64_t si = (int64_t)pr.ti * kTile + wi * 32 + l32;
         const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
-        Acc<PREC, SCHED, LG> acc;
+        Acc<PREC, SCHED, LW> acc;
 #pragma unroll
-        for (int m = 0; m < LG; ++m)
+        for (int m = 0; m < LW; ++m)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc.v[m][r] = 0.0f;
         if constexpr (PREC != SDC_PREC_FP32 && !TWO) {
 #pragma unroll
-            for (int m = 0; m < LG; ++m)
+            for (int m = 0; m < LW; ++m)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc.s[m][r] = 0.0f;
         }
@@ -459,9 +457,9 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
             kk = kk < nk ? kk : nk - 1;
             const Elem* pb;
             if constexpr (PAIRED) {
-                const int alpha = kk / n_c, c = kk - alpha * n_c;
-                b.a = Ab[(int64_t)(alpha * a.O8 + 2 * c + h) * a.n_pad + si];
-                pb = Bb + (int64_t)(alpha * a.F8 + 2 * c + h + ublk) * a.n_pad + sj;
+                const int alpha = kk / n_c, cc = kk - alpha * n_c;
+                b.a = Ab[(int64_t)(alpha * a.O8 + 2 * cc + h) * a.n_pad + si];
+                pb = Bb + (int64_t)(alpha * a.F8 + 2 * cc + h + ublk) * a.n_pad + sj;
             } else {
                 // block indices of both lane halves from the step index
                 // (uniform); A: [3][O8] blocks flattened, then the zero block
@@ -485,7 +483,8 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
             if constexpr (RADIAL) {
                 if (a.keys) {
                     // the pair's shells, computed once per plan for all lag groups
-                    const uint4* kp = (const uint4*)(a.keys + (((int64_t)p * 4 + wave) * 64 + lane) * 16);
+                    const uint4* kp =
+                        (const uint4*)(a.keys + (((int64_t)p * 4 + c.quadrant) * 64 + lane) * 16);
                     const uint4 k0 = kp[0], k1 = kp[1];
                     const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
 #pragma unroll
@@ -496,7 +495,7 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
                     for (int r = 0; r < 16; ++r) {
                         const float4 pi = *(const float4*)(a.pos4 + 4 * (rowbase + 8 * (r / 4) + (r % 4)));
                         const float d2 = dist2_f32(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
-                        bin[r] = shell_of(d2, e2s, a.n_shells, a.inv_w);
+                        bin[r] = shell_of(d2, c.e2s, a.n_shells, a.inv_w);
                     }
                 }
             } else {
@@ -507,17 +506,17 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         };
         auto add_hist = [&](auto with_small) {
 #pragma unroll
-            for (int m = 0; m < LG; ++m) {
-                if ((grp.mask >> m) & 1) {
+            for (int m = 0; m < LW; ++m) {
+                if ((grp.mask >> (OFF + m)) & 1) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         double v = (double)acc.v[m][r];
                         if constexpr (decltype(with_small)::value) v += (double)acc.s[m][r];
                         if (a.det)
-                            atomicAdd(reinterpret_cast<unsigned long long*>(hist) + m * a.win + bin[r],
+                            atomicAdd(reinterpret_cast<unsigned long long*>(hist) + (OFF + m) * a.win + bin[r],
                                       to_fixed(v));
                         else
-                            atomicAdd(&hist[m * a.win + bin[r]], v);
+                            atomicAdd(&hist[(OFF + m) * a.win + bin[r]], v);
                     }
                 }
             }
@@ -526,20 +525,62 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
         if constexpr (TWO) {
             // small products first, while the sums are still small, then the
             // large ones on top (see the pass constants)
-            k_loop<PREC, kPassSmall, SCHED, NB, LG, kStagesTwoPassSmall>(nk, load, acc);
-            k_loop<PREC, kPassLarge, SCHED, NB, LG, kStagesTwoPassLarge>(nk, load, acc);
+            k_loop<PREC, kPassSmall, SCHED, NB, LW, OFF, kStagesTwoPassSmall>(nk, load, acc);
+            k_loop<PREC, kPassLarge, SCHED, NB, LW, OFF, kStagesTwoPassLarge>(nk, load, acc);
             bins();
             add_hist(std::false_type{});
         } else {
-            k_loop<PREC, kPassAll, SCHED, NB, LG, kStagesOnePass>(nk, load, acc);
+            k_loop<PREC, kPassAll, SCHED, NB, LW, OFF, kStagesOnePass>(nk, load, acc);
             bins();
             add_hist(std::integral_constant<bool, PREC != SDC_PREC_FP32>{});
         }
     }
+}
+
+// One task of a plan: the stream's tile pairs for one lag group, histogram
+// in LDS (`hist`: [LG][win] FP64, then the radial edge table), merged into
+// the plan's global bins at the end.  Called by the whole workgroup.
+// PAIRED: O8 is even, so a K-step's two origin blocks always lie in one
+// component and the block offsets follow from the step with one scalar
+// division; otherwise the blocks of all components are taken in turn and a
+// step may straddle two components.
+// SCHED: kSchedOnePass, kSchedTwoPass (hi/lo splits only) or kSchedLagSplit
+// (eight waves: wave w takes quadrant w mod 4 and the lag half w / 4).
+template <int PREC, int RADIAL, int PAIRED, int SCHED>
+__device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double* hist) {
+    constexpr int LG = lag_group(PREC);
+    constexpr int NT = threads_per_wg(SCHED);
+    float* e2s = (float*)(hist + LG * a.win);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    TaskCtx c;
+    c.a = &a;
+    c.grp = a.groups[task % a.n_groups];
+    c.st = a.streams[task / a.n_groups];
+    c.hist = hist;
+    c.e2s = e2s;
+    c.quadrant = wave & 3;
+
+    for (int x = tid; x < LG * a.win; x += NT) hist[x] = 0.0;
+    if constexpr (RADIAL) {
+        for (int x = tid; x < a.n_shells; x += NT) e2s[x] = a.e2[x];
+    }
+    __syncthreads();
+
+    if constexpr (SCHED == kSchedLagSplit) {
+        if (wave < 4)
+            pair_loop<PREC, RADIAL, PAIRED, SCHED, LG / 2, 0>(c);
+        else
+            pair_loop<PREC, RADIAL, PAIRED, SCHED, LG / 2, LG / 2>(c);
+    } else {
+        pair_loop<PREC, RADIAL, PAIRED, SCHED, LG, 0>(c);
+    }
     __syncthreads();
 
     // Merge the stream's histogram into the global bins.
-    for (int x = tid; x < LG * a.win; x += 256) {
+    const KGroup grp = c.grp;
+    const KStream st = c.st;
+    for (int x = tid; x < LG * a.win; x += NT) {
         const int m = x / a.win;
         const int w = x - m * a.win;
         const double v = hist[x];
@@ -568,7 +609,7 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
 }
 
 template <int PREC, int RADIAL, int PAIRED, int SCHED>
-__global__ __launch_bounds__(256, wg_per_cu(SCHED)) void fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused_kernel(FusedArgs a) {
     extern __shared__ double hist[];
     // XCD-aware task order: consecutive tasks land on the same XCD (work-
     // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
@@ -592,7 +633,7 @@ __global__ __launch_bounds__(256, wg_per_cu(SCHED)) void fused_kernel(FusedArgs 
 // K-step addressing follows each plan's origin-block count (per component
 // when it is even).
 template <int PREC, int RADIAL, int SCHED>
-__global__ __launch_bounds__(256, wg_per_cu(SCHED)) void fused_batch_kernel(
+__global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused_batch_kernel(
     const FusedArgs* __restrict__ args, const int64_t* __restrict__ task_start, int n_plans,
     unsigned* __restrict__ queue, int per, int total) {
     extern __shared__ double hist[];
@@ -666,24 +707,27 @@ static const void* pick_fused(int radial, int paired, bool batch) {
     return paired ? fused_fn<PREC, SCHED, 0, 1>() : fused_fn<PREC, SCHED, 0, 0>();
 }
 
+template <int PREC>
+static const void* pick_sched(int sched, int radial, int paired, bool batch) {
+    switch (sched) {
+        case kSchedOnePass: return pick_fused<PREC, kSchedOnePass>(radial, paired, batch);
+        case kSchedLagSplit: return pick_fused<PREC, kSchedLagSplit>(radial, paired, batch);
+        case kSchedTwoPass:
+            if constexpr (PREC == SDC_PREC_SPLIT_BF16 || PREC == SDC_PREC_SPLIT_FP16)
+                return pick_fused<PREC, kSchedTwoPass>(radial, paired, batch);
+            return nullptr;
+        default: return nullptr;
+    }
+}
+
 // Kernel of a fused launch, or null for a (precision, schedule) pair that
 // does not exist.
 static const void* fused_kernel_of(int precision, int sched, int radial, int paired, bool batch) {
     switch (precision) {
-        case SDC_PREC_FP32:
-            return sched == kSchedOnePass ? pick_fused<SDC_PREC_FP32, kSchedOnePass>(radial, paired, batch)
-                                          : nullptr;
-        case SDC_PREC_BF16X3:
-            return sched == kSchedOnePass ? pick_fused<SDC_PREC_BF16X3, kSchedOnePass>(radial, paired, batch)
-                                          : nullptr;
-        case SDC_PREC_SPLIT_BF16:
-            return sched == kSchedOnePass
-                       ? pick_fused<SDC_PREC_SPLIT_BF16, kSchedOnePass>(radial, paired, batch)
-                       : pick_fused<SDC_PREC_SPLIT_BF16, kSchedTwoPass>(radial, paired, batch);
-        case SDC_PREC_SPLIT_FP16:
-            return sched == kSchedOnePass
-                       ? pick_fused<SDC_PREC_SPLIT_FP16, kSchedOnePass>(radial, paired, batch)
-                       : pick_fused<SDC_PREC_SPLIT_FP16, kSchedTwoPass>(radial, paired, batch);
+        case SDC_PREC_FP32: return pick_sched<SDC_PREC_FP32>(sched, radial, paired, batch);
+        case SDC_PREC_BF16X3: return pick_sched<SDC_PREC_BF16X3>(sched, radial, paired, batch);
+        case SDC_PREC_SPLIT_BF16: return pick_sched<SDC_PREC_SPLIT_BF16>(sched, radial, paired, batch);
+        case SDC_PREC_SPLIT_FP16: return pick_sched<SDC_PREC_SPLIT_FP16>(sched, radial, paired, batch);
         default: return nullptr;
     }
 }
@@ -697,14 +741,14 @@ int launch_fused(const FusedArgs& a, void* stream) {
     const int n_tasks = a.n_groups * a.n_streams;
     const int grid = 8 * ((n_tasks + 7) / 8);
     void* params[] = {(void*)&a};
-    return (int)hipLaunchKernel(fn, dim3(grid), dim3(256), params, lds, (hipStream_t)stream);
+    return (int)hipLaunchKernel(fn, dim3(grid), dim3(threads_per_wg(a.sched)), params, lds, (hipStream_t)stream);
 }
 
 int batch_grid(int precision, int sched, int radial, int lds, int device, int total, int* grid) {
     const void* fn = fused_kernel_of(precision, sched, radial, 0, true);
     if (!fn) return (int)hipErrorInvalidValue;
     int per_cu = 0, n_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_per_wg(sched), lds);
     if (e != hipSuccess) return (int)e;
     e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return (int)e;
@@ -730,7 +774,8 @@ int launch_fused_batch(const BatchLaunch& b, void* stream) {
     int total = b.total;
     void* params[] = {(void*)&args, (void*)&task_start, (void*)&n_plans, (void*)&queue, (void*)&per,
                       (void*)&total};
-    return (int)hipLaunchKernel(fn, dim3(b.grid), dim3(256), params, b.lds, (hipStream_t)stream);
+    return (int)hipLaunchKernel(fn, dim3(b.grid), dim3(threads_per_wg(b.sched)), params, b.lds,
+                                (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,7 +1111,7 @@ int launch_self(const SelfArgs& a, void* stream) {
 // calls (they stay legal under stream capture).
 int prepare_kernels() {
     for (int prec = SDC_PREC_FP32; prec <= SDC_PREC_BF16X3; ++prec)
-        for (int sched = kSchedOnePass; sched <= kSchedTwoPass; ++sched)
+        for (int sched = kSchedOnePass; sched <= kSchedLagSplit; ++sched)
             for (int k = 0; k < 6; ++k) {  // (radial, paired) of the single-plan kernels, then the batch ones
                 const bool batch = k >= 4;
                 const int radial = batch ? (k & 1) : ((k >> 1) & 1), paired = batch ? 0 : (k & 1);

@@ -45,6 +45,7 @@ struct TuneEntry {
     TuneKey key;
     sdc_tuning tuning{};
     double fused_ms = 0.0;
+    std::string candidates;  // "schedule/segment:ms ..." of every candidate timed
 };
 
 // Size class of a sample: floor(2 log2 N) (half octaves), and the K-steps of
@@ -115,6 +116,8 @@ bool parse_entry(const std::string& obj, TuneEntry* e) {
         if (key == "arch") {
             e->key.arch = val;
             have |= 1;
+        } else if (key == "candidates") {
+            e->candidates = val;
         } else if (is_num) {
             if (key == "kind") e->key.kind = (int)num, have |= 2;
             else if (key == "n_class") e->key.n_class = (int)num, have |= 4;
@@ -168,9 +171,9 @@ bool write_file(const char* path, std::vector<TuneEntry> entries) {
         const TuneEntry& e = entries[k];
         std::fprintf(f,
                      "  {\"arch\": \"%s\", \"kind\": %d, \"n_class\": %d, \"k_steps\": %d, \"precision\": %d, "
-                     "\"schedule\": %d, \"segment_pairs\": %d, \"fused_ms\": %.4f}%s\n",
+                     "\"schedule\": %d, \"segment_pairs\": %d, \"fused_ms\": %.4f, \"candidates\": \"%s\"}%s\n",
                      e.key.arch.c_str(), e.key.kind, e.key.n_class, e.key.k_steps, e.key.precision,
-                     (int)e.tuning.schedule, (int)e.tuning.segment_pairs, e.fused_ms,
+                     (int)e.tuning.schedule, (int)e.tuning.segment_pairs, e.fused_ms, e.candidates.c_str(),
                      k + 1 < entries.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
@@ -198,7 +201,7 @@ sdc_status resolve_tuning(const sdc_tuning* given, int64_t n_sites, const sdc_bi
                           const sdc_corr_spec* corr, int device, sdc_tuning* out) {
     sdc_tuning t{};
     if (given) t = *given;
-    if (t.schedule < SDC_SCHED_DEFAULT || t.schedule > SDC_SCHED_TWO_PASS)
+    if (t.schedule < SDC_SCHED_DEFAULT || t.schedule > SDC_SCHED_LAG_SPLIT)
         return set_error(SDC_ERR_INVALID_ARG, "unknown schedule");
     if (t.segment_pairs < 0 || t.segment_pairs > kMaxSegmentPairs)
         return set_error(SDC_ERR_INVALID_ARG, "segment_pairs must be 0 or in [1, 2^20]");
@@ -216,7 +219,7 @@ sdc_status resolve_tuning(const sdc_tuning* given, int64_t n_sites, const sdc_bi
     }
     if (t.schedule == SDC_SCHED_DEFAULT)
         t.schedule = split_precision(corr->precision) ? SDC_SCHED_TWO_PASS : SDC_SCHED_ONE_PASS;
-    if (t.schedule != SDC_SCHED_ONE_PASS && t.schedule != SDC_SCHED_TWO_PASS)
+    if (t.schedule < SDC_SCHED_ONE_PASS || t.schedule > SDC_SCHED_LAG_SPLIT)
         return set_error(SDC_ERR_INVALID_ARG, "unknown schedule in the tuning file");
     if (!sched_valid(corr->precision, sched_index(t.schedule)))
         return set_error(SDC_ERR_UNSUPPORTED, "schedule not available for this precision");
@@ -243,20 +246,48 @@ sdc_status sdc_tuning_lookup(const char* cache_path, int64_t n_sites, const sdc_
     return SDC_OK;
 }
 
+sdc_status sdc_autotune_candidates(const sdc_bin_spec* bins, const sdc_corr_spec* corr, sdc_tuning* out,
+                                   int32_t max_out, int32_t* n_out) {
+    if (!bins || !corr || !n_out || (max_out > 0 && !out)) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
+    std::vector<int32_t> schedules = {SDC_SCHED_ONE_PASS, SDC_SCHED_LAG_SPLIT};
+    if (split_precision(corr->precision)) schedules.push_back(SDC_SCHED_TWO_PASS);
+    std::vector<int32_t> segments;
+    if (bins->kind == SDC_BINS_RADIAL) segments = {64, 256, sdc::kMaxSegmentPairs};
+    else segments = {24, 48, 96, 192, 384};
+    int32_t n = 0;
+    for (int32_t sch : schedules)
+        for (int32_t seg : segments) {
+            if (n < max_out) out[n] = sdc_tuning{sch, seg};
+            ++n;
+        }
+    *n_out = n;
+    sdc::set_error(SDC_OK, "");
+    return SDC_OK;
+}
+
 sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_bin_spec* bins,
-                        const sdc_corr_spec* corr, int device, int32_t max_lags, const char* cache_path,
-                        sdc_tuning* best, double* best_ms) {
+                        const sdc_corr_spec* corr, int device, int32_t max_lags, const sdc_tuning* candidates,
+                        int32_t n_candidates, const char* cache_path, sdc_tuning* best, double* best_ms,
+                        double* candidate_ms) {
     if (!positions_host || !bins || !corr || !best) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
     std::string arch;
     sdc_status s = device_arch(device, &arch);
     if (s != SDC_OK) return s;
     if (corr->n_lags < 1 || corr->n_origins < 1 || corr->origin_stride < 1)
         return sdc::set_error(SDC_ERR_INVALID_ARG, "invalid correlation spec");
-    std::vector<int32_t> schedules = {SDC_SCHED_ONE_PASS};
-    if (split_precision(corr->precision)) schedules.push_back(SDC_SCHED_TWO_PASS);
-    std::vector<int32_t> segments;
-    if (bins->kind == SDC_BINS_RADIAL) segments = {64, 256, sdc::kMaxSegmentPairs};
-    else segments = {24, 48, 96, 192, 384};
+    std::vector<sdc_tuning> cands;
+    if (candidates) {
+        if (n_candidates < 1 || n_candidates > 4096) return sdc::set_error(SDC_ERR_INVALID_ARG, "n_candidates");
+        cands.assign(candidates, candidates + n_candidates);
+    } else {
+        int32_t n = 0;
+        sdc_autotune_candidates(bins, corr, nullptr, 0, &n);
+        cands.resize(n);
+        sdc_autotune_candidates(bins, corr, cands.data(), n, &n);
+    }
+    for (const sdc_tuning& t : cands)
+        if (t.schedule == SDC_SCHED_DEFAULT || t.segment_pairs == 0)
+            return sdc::set_error(SDC_ERR_INVALID_ARG, "candidates must set every field");
 
     const int n_use = max_lags > 0 ? std::min(max_lags, corr->n_lags) : corr->n_lags;
     std::vector<int32_t> lags(n_use);
@@ -278,9 +309,10 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
     c.flags |= SDC_FLAG_TIMING;
     double best_t = 0.0;
     bool have = false;
-    for (int32_t sched : schedules) {
-        for (int32_t seg : segments) {
-            sdc_tuning cand{sched, seg};
+    std::string summary;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        {
+            const sdc_tuning cand = cands[ci];
             sdc_plan* p = nullptr;
             s = sdc_plan_create_tuned(positions_host, n_sites, bins, &c, &cand, device, &p);
             if (s != SDC_OK) {
@@ -302,6 +334,11 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
             }
             std::sort(ms.begin(), ms.end());
             const double med = ms[ms.size() / 2];
+            if (candidate_ms) candidate_ms[ci] = med;
+            char buf[64];
+            std::snprintf(buf, sizeof buf, "%s%d/%d:%.3f", summary.empty() ? "" : " ", (int)cand.schedule,
+                          (int)cand.segment_pairs, med);
+            summary += buf;
             if (!have || med < best_t) {
                 best_t = med;
                 *best = cand;
@@ -319,6 +356,7 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
         ne.key = key;
         ne.tuning = *best;
         ne.fused_ms = best_t;
+        ne.candidates = summary;
         v.push_back(ne);
         if (!write_file(cache_path, v)) return sdc::set_error(SDC_ERR_INVALID_ARG, "cannot write the tuning file");
     }

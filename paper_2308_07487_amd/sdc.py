@@ -56,8 +56,9 @@ class Tuning(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("segment_pairs", ctypes.c_int32)]
 
 
-SCHED_DEFAULT, SCHED_ONE_PASS, SCHED_TWO_PASS = 0, 1, 2
-SCHEDULES = {"default": SCHED_DEFAULT, "one_pass": SCHED_ONE_PASS, "two_pass": SCHED_TWO_PASS}
+SCHED_DEFAULT, SCHED_ONE_PASS, SCHED_TWO_PASS, SCHED_LAG_SPLIT = 0, 1, 2, 3
+SCHEDULES = {"default": SCHED_DEFAULT, "one_pass": SCHED_ONE_PASS, "two_pass": SCHED_TWO_PASS,
+             "lag_split": SCHED_LAG_SPLIT}
 
 
 class SqSpec(ctypes.Structure):
@@ -83,7 +84,9 @@ EXPORTS = ("sdc_plan_create", "sdc_plan_n_bins", "sdc_accumulate", "sdc_finalize
            "sdc_mc_anneal", "sdc_mc_create", "sdc_mc_run", "sdc_mc_timings", "sdc_mc_uses_stencil",
            "sdc_mc_destroy", "sdc_plan_create_tuned", "sdc_plan_get_tuning", "sdc_autotune",
            "sdc_tuning_lookup", "sdc_batch_create_tuned", "sdc_batch_schedule",
-           "sdc_plan_structure_factor_static")
+           "sdc_plan_structure_factor_static", "sdc_mfma_peak", "sdc_mfma_probe",
+           "sdc_autotune_candidates")
+MFMA_FORMS = {"bf16": 0, "f16": 1, "f32": 2}
 FLAG_TIMING = 1
 FLAG_CONNECTED = 2
 FLAG_NO_KEY_TABLE = 4
@@ -108,7 +111,10 @@ def lib():
                                             ctypes.POINTER(Tuning), ctypes.c_int, ctypes.POINTER(P)]
         L.sdc_plan_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.sdc_autotune.argtypes = [P, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec), ctypes.c_int,
-                                   i32, ctypes.c_char_p, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]
+                                   i32, P, i32, ctypes.c_char_p, ctypes.POINTER(Tuning),
+                                   ctypes.POINTER(ctypes.c_double), P]
+        L.sdc_autotune_candidates.argtypes = [ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec), P, i32,
+                                              ctypes.POINTER(i32)]
         L.sdc_tuning_lookup.argtypes = [ctypes.c_char_p, i64, ctypes.POINTER(BinSpec), ctypes.POINTER(CorrSpec),
                                         ctypes.c_int, ctypes.POINTER(Tuning), ctypes.POINTER(i32)]
         L.sdc_batch_create_tuned.argtypes = [P, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(P)]
@@ -133,6 +139,9 @@ def lib():
         L.sdc_batch_destroy.argtypes = [P]
         L.sdc_plan_structure_factor.argtypes = [P, P, i32, P, P, P]
         L.sdc_plan_structure_factor_static.argtypes = [P, P, i32, P, P, P]
+        L.sdc_mfma_peak.argtypes = [i32, i32, i64, i32, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.sdc_mfma_probe.argtypes = [i32, ctypes.c_float, P, P, i32, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
         L.sdc_mc_n_sweeps.argtypes = [ctypes.POINTER(McSpec), ctypes.POINTER(i64)]
         L.sdc_mc_anneal.argtypes = [P, i64, ctypes.POINTER(McSpec), P, P, P, P, ctypes.c_int, P]
         L.sdc_mc_create.argtypes = [P, i64, ctypes.POINTER(McSpec), ctypes.c_int, ctypes.POINTER(P)]
@@ -220,19 +229,32 @@ def _tuning_dict(t):
 
 
 def autotune(positions, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0), n_shells=0,
-             r_max=0.0, origin_stride=1, connected=False, device=0, max_lags=64, cache_path=None):
-    """Times every candidate tuning of this sample shape on the device
-    (sdc_autotune); returns ({"schedule", "segment_pairs"}, median fused ms).
-    With cache_path the winner is written to that JSON tuning file."""
+             r_max=0.0, origin_stride=1, connected=False, device=0, max_lags=0, candidates=None, cache_path=None):
+    """Times candidate tunings of this sample shape on the device
+    (sdc_autotune).  candidates: list of (schedule, segment_pairs), or None for
+    the built-in list.  Returns (best {"schedule", "segment_pairs"}, its
+    median fused ms, [(candidate dict, median ms), ...]).  With cache_path the
+    winner is written to that JSON tuning file."""
     pos = np.ascontiguousarray(positions, dtype=np.float32)
     bs = bin_spec(kind, cells, n_shells, r_max)
     cs = corr_spec(n_origins, n_lags, precision, origin_stride, flags=FLAG_CONNECTED if connected else 0)
+    if candidates is None:
+        n = ctypes.c_int32()
+        _check(lib().sdc_autotune_candidates(ctypes.byref(bs), ctypes.byref(cs), None, 0, ctypes.byref(n)),
+               "sdc_autotune_candidates")
+        arr = (Tuning * n.value)()
+        _check(lib().sdc_autotune_candidates(ctypes.byref(bs), ctypes.byref(cs), ctypes.cast(arr, ctypes.c_void_p),
+                                             n.value, ctypes.byref(n)), "sdc_autotune_candidates")
+    else:
+        arr = (Tuning * len(candidates))(*[tuning(sch, seg) for sch, seg in candidates])
+    times = np.zeros(len(arr))
     best = Tuning()
     ms = ctypes.c_double()
     _check(lib().sdc_autotune(_np_ptr(pos), pos.shape[0], ctypes.byref(bs), ctypes.byref(cs), int(device),
-                              int(max_lags), cache_path.encode() if cache_path else None, ctypes.byref(best),
-                              ctypes.byref(ms)), "sdc_autotune")
-    return _tuning_dict(best), float(ms.value)
+                              int(max_lags), ctypes.cast(arr, ctypes.c_void_p), len(arr),
+                              cache_path.encode() if cache_path else None, ctypes.byref(best), ctypes.byref(ms),
+                              _np_ptr(times)), "sdc_autotune")
+    return _tuning_dict(best), float(ms.value), [(_tuning_dict(t), float(x)) for t, x in zip(arr, times)]
 
 
 def tuning_lookup(cache_path, n_sites, kind, n_origins, n_lags, precision="split_bf16", cells=(0, 0, 0),
@@ -245,6 +267,25 @@ def tuning_lookup(cache_path, n_sites, kind, n_origins, n_lags, precision="split
     _check(lib().sdc_tuning_lookup(cache_path.encode(), int(n_sites), ctypes.byref(bs), ctypes.byref(cs),
                                    int(device), ctypes.byref(t), ctypes.byref(found)), "sdc_tuning_lookup")
     return _tuning_dict(t) if found.value else None
+
+
+def mfma_peak(form="bf16", random_operands=True, iterations=20000, workgroups_per_cu=2, device=0):
+    """Sustained MFMA rate (sdc_mfma_peak): (ms of the timed launch, executed TFLOP/s)."""
+    ms, tf = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sdc_mfma_peak(MFMA_FORMS[form], int(bool(random_operands)), int(iterations),
+                               int(workgroups_per_cu), int(device), ctypes.byref(ms), ctypes.byref(tf)),
+           "sdc_mfma_peak")
+    return float(ms.value), float(tf.value)
+
+
+def mfma_probe(form, c, a, b, device=0):
+    """c + sum_k a[k] b[k] through one MFMA instruction of the form (sdc_mfma_probe)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    out = ctypes.c_float()
+    _check(lib().sdc_mfma_probe(MFMA_FORMS[form], float(c), _np_ptr(a), _np_ptr(b), a.shape[0], int(device),
+                                ctypes.byref(out)), "sdc_mfma_probe")
+    return float(out.value)
 
 
 def layout_keys(positions, kind, cells=(0, 0, 0), n_shells=0, r_max=0.0):

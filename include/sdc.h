@@ -146,9 +146,13 @@ typedef enum {
     SDC_SCHED_TWO_PASS = 2, /* SPLIT_BF16 / SPLIT_FP16 only: per tile pair a K loop over
                                hi*lo + lo*hi, then one adding hi*hi to those sums, in one
                                accumulator set; two workgroups per compute unit. */
-    SDC_SCHED_LAG_SPLIT = 3 /* one K loop, second accumulator set as ONE_PASS, but workgroups
+    SDC_SCHED_LAG_SPLIT = 3,/* one K loop, second accumulator set as ONE_PASS, but workgroups
                                of eight waves: two waves per 32x32 quadrant, each with half
                                of the lags; two waves per SIMD.  Every precision. */
+    SDC_SCHED_FOLD = 4      /* reduced forms only: one K loop; per K-step the small products
+                               are summed from zero in a transient tile and added to the
+                               large sums with FP32 vector adds (round to nearest); one
+                               accumulator set, two workgroups per compute unit. */
 } sdc_schedule;
 
 /* Tuning of a plan: what the autotuner (sdc_autotune) chooses per size

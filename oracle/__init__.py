@@ -92,7 +92,7 @@ def lib():
         L.oracle_ll_rk4_full.argtypes = [i64, P, P, P, P, f64, f64, P, f64, i64, P]
         L.oracle_mc_n_sweeps.argtypes = [f64, f64, f64, i64, i64, P]
         L.oracle_mc_anneal.argtypes = [i64, P, P, P, P, f64, f64, u64, f64, f64, f64, i64, i64, f64, f64,
-                                       P, P, P, P]
+                                       P, P, P, P, ctypes.c_int]
         L.oracle_philox.argtypes = [u64, u32, i64, i64, P]
         L.oracle_init_state.argtypes = [u64, i64, ctypes.c_int, f64, P]
         L.oracle_philox_block.argtypes = [P, P, P]
@@ -406,10 +406,13 @@ def mc_n_sweeps(T_start, T_end, cool, sweeps_per_T, sweeps_final):
 
 
 def mc_anneal(row, col, J, init, seed, T_start, T_end, cool, sweeps_per_T, sweeps_final,
-              cone0=np.pi, acc_target=0.2, D=None, A=0.0, Hz=0.0):
+              cone0=np.pi, acc_target=0.2, D=None, A=0.0, Hz=0.0, site_order=False):
     """Annealed Metropolis sweeps with an adaptive cone (Sec. 2.1, Sec. 4.3) on
-    CSR bonds with the Hamiltonian of Eq. (1).  Returns (state [n][3] FP64,
-    accepted moves per sweep, energy per site, final cone, last T, colours)."""
+    CSR bonds with the Hamiltonian of Eq. (1).  Sweeps visit the greedy colour
+    classes in turn (the order a parallel sweep reproduces move for move), or
+    with ``site_order`` the sites in plain index order (the sequential sweep).
+    Returns (state [n][3] FP64, accepted moves per sweep, energy per site,
+    final cone, last T, colour classes visited)."""
     row = np.ascontiguousarray(row, dtype=np.int64)
     col = np.ascontiguousarray(col, dtype=np.int32)
     J = np.ascontiguousarray(J, dtype=np.float64)
@@ -427,7 +430,7 @@ def mc_anneal(row, col, J, init, seed, T_start, T_end, cool, sweeps_per_T, sweep
     _check(lib().oracle_mc_anneal(n, _ptr(row), _ptr(col), _ptr(J), Dp, float(A), float(Hz), int(seed),
                                   float(T_start), float(T_end), float(cool), int(sweeps_per_T),
                                   int(sweeps_final), float(cone0), float(acc_target), _ptr(init),
-                                  _ptr(state), _ptr(acc), _ptr(info)), "mc_anneal")
+                                  _ptr(state), _ptr(acc), _ptr(info), int(bool(site_order))), "mc_anneal")
     return state, acc[:ns], float(info[0]), float(info[1]), float(info[2]), int(info[3])
 
 

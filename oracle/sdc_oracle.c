@@ -804,14 +804,20 @@ static void ofield(int64_t i, const int64_t *row, const int32_t *col, const doub
  * u_2 < exp(-dE / T).  After each sweep, rate = accepted / n: cone *= 0.9
  * (not below 1e-3) when rate < acc_target, cone = min(pi, 1.1 cone) when
  * rate > 2 acc_target.
+ * site_order != 0 visits the sites in plain index order instead (the
+ * textbook sequential sweep; the same draws per site and sweep): the colour
+ * classes are a visiting order chosen so that a parallel sweep can reproduce
+ * it move for move, and both orders leave the Boltzmann distribution
+ * invariant.
  * init: [n][3] fp32; state_out: [n][3] fp64; accepted_out: [n_sweeps] or
- * NULL; info_out[4]: energy per site (Eq. (1)), final cone, last T, colours.
+ * NULL; info_out[4]: energy per site (Eq. (1)), final cone, last T, colour
+ * classes visited (1 in site order).
  */
 int oracle_mc_anneal(int64_t n, const int64_t *row, const int32_t *col, const double *J,
                      const double *Dv, double A, double Hz, uint64_t seed, double T_start,
                      double T_end, double cool, int64_t sweeps_per_T, int64_t sweeps_final,
                      double cone0, double acc_target, const float *init, double *state_out,
-                     int64_t *accepted_out, double *info_out) {
+                     int64_t *accepted_out, double *info_out, int site_order) {
     const double pi = 3.14159265358979323846;
     if (n <= 0 || !(cone0 > 0.0 && cone0 <= pi)) return OR_EINVAL;
     int64_t n_sweeps = 0;
@@ -824,7 +830,11 @@ int oracle_mc_anneal(int64_t n, const int64_t *row, const int32_t *col, const do
         return OR_ENOMEM;
     }
     omc_schedule(T_start, T_end, cool, sweeps_per_T, sweeps_final, T_of, n_sweeps);
-    const int32_t n_col = ocolour(n, row, col, colour);
+    int32_t n_col = ocolour(n, row, col, colour);
+    if (site_order) {
+        for (int64_t i = 0; i < n; ++i) colour[i] = 0;
+        n_col = 1;
+    }
     double *S = state_out;
     for (int64_t x = 0; x < 3 * n; ++x) S[x] = (double)init[x];
     double cone = cone0;

@@ -941,17 +941,17 @@ sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32
     // tunings give the most work (pair-terms times origins).
     int schedule = tuning ? tuning->schedule : SDC_SCHED_DEFAULT;
     if (schedule != SDC_SCHED_DEFAULT) {
-        if (schedule < SDC_SCHED_ONE_PASS || schedule > SDC_SCHED_LAG_SPLIT)
+        if (schedule < SDC_SCHED_ONE_PASS || schedule > SDC_SCHED_FOLD)
             return set_err(SDC_ERR_INVALID_ARG, "unknown schedule");
         if (!sdc::sched_valid(prec, sdc::sched_index(schedule)))
             return set_err(SDC_ERR_UNSUPPORTED, "schedule not available for this precision");
     } else {
-        double w[4] = {0.0, 0.0, 0.0, 0.0};
+        double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         for (int k = 0; k < n_plans; ++k)
             w[plans[k]->tuning.schedule] += (double)plans[k]->lay.n * (double)plans[k]->lay.n *
                                              plans[k]->corr.n_lags * plans[k]->corr.n_origins;
         schedule = SDC_SCHED_ONE_PASS;
-        for (int sch = SDC_SCHED_TWO_PASS; sch <= SDC_SCHED_LAG_SPLIT; ++sch)
+        for (int sch = SDC_SCHED_TWO_PASS; sch <= SDC_SCHED_FOLD; ++sch)
             if (w[sch] > w[schedule]) schedule = sch;
     }
     SDC_HIP(hipSetDevice(device), "hipSetDevice");

@@ -35,22 +35,30 @@ constexpr int lag_group(int precision) { return precision == SDC_PREC_FP32 ? 16 
 //    waves in which two waves share each 32x32 quadrant and take half of the
 //    lag group each: 2 x 64 accumulator registers for the reduced forms (128
 //    for FP32), two waves per SIMD.  Every precision.
-constexpr int kSchedOnePass = 0, kSchedTwoPass = 1, kSchedLagSplit = 2;
+//  kSchedFold: reduced forms only: one K loop; per K-step and lag the
+//    small products are summed from zero in a transient 32x32 tile and added
+//    to the large sums with FP32 vector adds (round to nearest, no bias),
+//    beside the hi*hi MFMA; 128 accumulator registers, two workgroups per
+//    CU.
+constexpr int kSchedOnePass = 0, kSchedTwoPass = 1, kSchedLagSplit = 2, kSchedFold = 3;
 constexpr int threads_per_wg(int sched) { return sched == kSchedLagSplit ? 512 : 256; }
 // Register buffers of the K loops (loads of NS - 1 K-steps ahead in flight).
 // At two workgroups per CU the other workgroup covers the rest of the load
 // latency: two to six buffers in either loop of the two-pass schedule time
 // the same (1085-1102 ms at sc 36^3), so the fewest registers win.
-constexpr int kStagesOnePass = 3, kStagesTwoPassSmall = 2, kStagesTwoPassLarge = 2;
+constexpr int kStagesOnePass = 3, kStagesTwoPassSmall = 2, kStagesTwoPassLarge = 2, kStagesFold = 2;
 // Kernel schedule of a public sdc_schedule (ONE_PASS or TWO_PASS).
 constexpr int sched_index(int schedule) {
-    return schedule == SDC_SCHED_TWO_PASS ? kSchedTwoPass
-                                          : (schedule == SDC_SCHED_LAG_SPLIT ? kSchedLagSplit : kSchedOnePass);
+    return schedule == SDC_SCHED_TWO_PASS  ? kSchedTwoPass
+           : schedule == SDC_SCHED_LAG_SPLIT ? kSchedLagSplit
+           : schedule == SDC_SCHED_FOLD      ? kSchedFold
+                                             : kSchedOnePass;
 }
-constexpr int wg_per_cu(int sched) { return sched == kSchedTwoPass ? 2 : 1; }
+constexpr int wg_per_cu(int sched) { return sched == kSchedTwoPass || sched == kSchedFold ? 2 : 1; }
 constexpr bool sched_valid(int precision, int sched) {
     return sched == kSchedOnePass || sched == kSchedLagSplit ||
-           (sched == kSchedTwoPass && (precision == SDC_PREC_SPLIT_BF16 || precision == SDC_PREC_SPLIT_FP16));
+           (sched == kSchedTwoPass && (precision == SDC_PREC_SPLIT_BF16 || precision == SDC_PREC_SPLIT_FP16)) ||
+           (sched == kSchedFold && precision != SDC_PREC_FP32);
 }
 // Pack elements (8 samples each) in one lane's B window: LG - 1 + 8 samples.
 constexpr int win_blocks(int lg) { return (lg + 14) / 8; }

@@ -224,7 +224,16 @@ __device__ inline f32x16 mfma16(uint4 a, uint4 b, f32x16 c) {
 // bias each element by a fraction of its last place per K-step.  Added to a
 // sum of their own size they keep every bit, and the large products added
 // afterwards (16 significant bits each) lose none either.
-constexpr int kPassAll = 0, kPassLarge = 1, kPassSmall = 2;
+//  kPassFold  : every product of the form; per K-step and lag the small
+//               products are summed from zero in a transient tile, which FP32
+//               vector adds (round to nearest) then add to acc.v, next to
+//               the hi*hi MFMA (fold schedule).
+constexpr int kPassAll = 0, kPassLarge = 1, kPassSmall = 2, kPassFold = 3;
+
+__device__ inline void add16(f32x16& acc, const f32x16& t) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += t[r];
+}
 
 // Three-product split for the wave's lag M (its window slice OFF + M):
 // hi*hi + hi*lo + lo*hi.
@@ -240,6 +249,12 @@ __device__ inline void split_step(const Chunk& av, const uint32_t (&wh)[NW],
             acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
             acc_s[M] = mfma16<PREC>(av.x, bl, acc_s[M]);
             acc_s[M] = mfma16<PREC>(av.y, bh, acc_s[M]);
+        } else if constexpr (PASS == kPassFold) {
+            f32x16 t = {};
+            t = mfma16<PREC>(av.x, bl, t);
+            t = mfma16<PREC>(av.y, bh, t);
+            acc[M] = mfma16<PREC>(av.x, bh, acc[M]);
+            add16(acc[M], t);
         } else {
             acc[M] = mfma16<PREC>(av.x, bl, acc[M]);
             acc[M] = mfma16<PREC>(av.y, bh, acc[M]);
@@ -264,11 +279,34 @@ __device__ inline void x3_step(const Chunk3& av, const uint32_t (&wh)[NW], const
     acc_s[M] = mfma16<SDC_PREC_BF16X3>(av.z, bh, acc_s[M]);
 }
 
+// The same with the small products folded into the main sums per K-step.
+template <int OFF, int M, int NW, int LW>
+__device__ inline void x3_fold_step(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
+                                    const uint32_t (&wl)[NW], f32x16 (&acc)[LW]) {
+    const uint4 bh = slice8<OFF + M, NW>(wh);
+    const uint4 bm = slice8<OFF + M, NW>(wm);
+    const uint4 bl = slice8<OFF + M, NW>(wl);
+    f32x16 t = {};
+    t = mfma16<SDC_PREC_BF16X3>(av.x, bm, t);
+    t = mfma16<SDC_PREC_BF16X3>(av.y, bh, t);
+    t = mfma16<SDC_PREC_BF16X3>(av.y, bm, t);
+    t = mfma16<SDC_PREC_BF16X3>(av.x, bl, t);
+    t = mfma16<SDC_PREC_BF16X3>(av.z, bh, t);
+    acc[M] = mfma16<SDC_PREC_BF16X3>(av.x, bh, acc[M]);
+    add16(acc[M], t);
+}
+
 template <int OFF, int NW, int LW, int... Ms>
 __device__ inline void x3_all(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
                               const uint32_t (&wl)[NW], f32x16 (&acc)[LW], f32x16 (&acc_s)[LW],
                               std::integer_sequence<int, Ms...>) {
     (x3_step<OFF, Ms, NW, LW>(av, wh, wm, wl, acc, acc_s), ...);
+}
+
+template <int OFF, int NW, int LW, int... Ms>
+__device__ inline void x3_fold_all(const Chunk3& av, const uint32_t (&wh)[NW], const uint32_t (&wm)[NW],
+                                   const uint32_t (&wl)[NW], f32x16 (&acc)[LW], std::integer_sequence<int, Ms...>) {
+    (x3_fold_step<OFF, Ms, NW, LW>(av, wh, wm, wl, acc), ...);
 }
 
 template <int PREC, int PASS, int OFF, int NW, int LW, int... Ms>
@@ -308,7 +346,7 @@ __device__ inline int pmod_dev(int a, int m) {
 template <int PREC, int SCHED, int LW>
 struct Acc {
     f32x16 v[LW];
-    f32x16 s[(PREC == SDC_PREC_FP32 || SCHED == kSchedTwoPass) ? 1 : LW];
+    f32x16 s[(PREC == SDC_PREC_FP32 || SCHED == kSchedTwoPass || SCHED == kSchedFold) ? 1 : LW];
 };
 
 // Operands of one K-step for one lane: A (8 origins, hi/lo or fp32) and the
@@ -337,7 +375,10 @@ __device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LW>&
                 wl[4 * k + e] = l4[e];
             }
         }
-        x3_all<OFF, NW, LW>(s.a, wh, wm, wl, acc, ac.s, std::make_integer_sequence<int, LW>{});
+        if constexpr (PASS == kPassFold)
+            x3_fold_all<OFF, NW, LW>(s.a, wh, wm, wl, acc, std::make_integer_sequence<int, LW>{});
+        else
+            x3_all<OFF, NW, LW>(s.a, wh, wm, wl, acc, ac.s, std::make_integer_sequence<int, LW>{});
     } else if constexpr (PREC == SDC_PREC_FP32) {
         float af[8], w[8 * NB];
         const uint32_t ar[8] = {s.a.x.x, s.a.x.y, s.a.x.z, s.a.x.w, s.a.y.x, s.a.y.y, s.a.y.z, s.a.y.w};
@@ -366,7 +407,7 @@ __device__ inline void stage_mma(const Stage<PREC, NB>& s, Acc<PREC, SCHED, LW>&
         }
         // the two-pass schedule has no second accumulator set (its passes
         // never write one)
-        if constexpr (SCHED == kSchedTwoPass)
+        if constexpr (SCHED == kSchedTwoPass || SCHED == kSchedFold)
             split_all<PREC, PASS, OFF, NW, LW>(s.a, wh, wl, acc, acc, std::make_integer_sequence<int, LW>{});
         else
             split_all<PREC, PASS, OFF, NW, LW>(s.a, wh, wl, acc, ac.s, std::make_integer_sequence<int, LW>{});
@@ -416,6 +457,7 @@ __device__ __forceinline__ void pair_loop(const TaskCtx& c) {
     constexpr int LG = lag_group(PREC);
     constexpr int NB = win_blocks(LG);
     constexpr bool TWO = SCHED == kSchedTwoPass;
+    constexpr bool FOLD = SCHED == kSchedFold;
     const FusedArgs& a = *c.a;
     const KGroup grp = c.grp;
     double* hist = c.hist;
@@ -443,7 +485,7 @@ __device__ __forceinline__ void pair_loop(const TaskCtx& c) {
         for (int m = 0; m < LW; ++m)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc.v[m][r] = 0.0f;
-        if constexpr (PREC != SDC_PREC_FP32 && !TWO) {
+        if constexpr (PREC != SDC_PREC_FP32 && !TWO && !FOLD) {
 #pragma unroll
             for (int m = 0; m < LW; ++m)
 #pragma unroll
@@ -527,6 +569,10 @@ __device__ __forceinline__ void pair_loop(const TaskCtx& c) {
             // large ones on top (see the pass constants)
             k_loop<PREC, kPassSmall, SCHED, NB, LW, OFF, kStagesTwoPassSmall>(nk, load, acc);
             k_loop<PREC, kPassLarge, SCHED, NB, LW, OFF, kStagesTwoPassLarge>(nk, load, acc);
+            bins();
+            add_hist(std::false_type{});
+        } else if constexpr (FOLD) {
+            k_loop<PREC, kPassFold, SCHED, NB, LW, OFF, kStagesFold>(nk, load, acc);
             bins();
             add_hist(std::false_type{});
         } else {
@@ -715,6 +761,9 @@ static const void* pick_sched(int sched, int radial, int paired, bool batch) {
         case kSchedTwoPass:
             if constexpr (PREC == SDC_PREC_SPLIT_BF16 || PREC == SDC_PREC_SPLIT_FP16)
                 return pick_fused<PREC, kSchedTwoPass>(radial, paired, batch);
+            return nullptr;
+        case kSchedFold:
+            if constexpr (PREC != SDC_PREC_FP32) return pick_fused<PREC, kSchedFold>(radial, paired, batch);
             return nullptr;
         default: return nullptr;
     }
@@ -1111,7 +1160,7 @@ int launch_self(const SelfArgs& a, void* stream) {
 // calls (they stay legal under stream capture).
 int prepare_kernels() {
     for (int prec = SDC_PREC_FP32; prec <= SDC_PREC_BF16X3; ++prec)
-        for (int sched = kSchedOnePass; sched <= kSchedLagSplit; ++sched)
+        for (int sched = kSchedOnePass; sched <= kSchedFold; ++sched)
             for (int k = 0; k < 6; ++k) {  // (radial, paired) of the single-plan kernels, then the batch ones
                 const bool batch = k >= 4;
                 const int radial = batch ? (k & 1) : ((k >> 1) & 1), paired = batch ? 0 : (k & 1);

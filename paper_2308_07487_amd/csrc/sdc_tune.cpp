@@ -201,7 +201,7 @@ sdc_status resolve_tuning(const sdc_tuning* given, int64_t n_sites, const sdc_bi
                           const sdc_corr_spec* corr, int device, sdc_tuning* out) {
     sdc_tuning t{};
     if (given) t = *given;
-    if (t.schedule < SDC_SCHED_DEFAULT || t.schedule > SDC_SCHED_LAG_SPLIT)
+    if (t.schedule < SDC_SCHED_DEFAULT || t.schedule > SDC_SCHED_FOLD)
         return set_error(SDC_ERR_INVALID_ARG, "unknown schedule");
     if (t.segment_pairs < 0 || t.segment_pairs > kMaxSegmentPairs)
         return set_error(SDC_ERR_INVALID_ARG, "segment_pairs must be 0 or in [1, 2^20]");
@@ -219,7 +219,7 @@ sdc_status resolve_tuning(const sdc_tuning* given, int64_t n_sites, const sdc_bi
     }
     if (t.schedule == SDC_SCHED_DEFAULT)
         t.schedule = split_precision(corr->precision) ? SDC_SCHED_TWO_PASS : SDC_SCHED_ONE_PASS;
-    if (t.schedule < SDC_SCHED_ONE_PASS || t.schedule > SDC_SCHED_LAG_SPLIT)
+    if (t.schedule < SDC_SCHED_ONE_PASS || t.schedule > SDC_SCHED_FOLD)
         return set_error(SDC_ERR_INVALID_ARG, "unknown schedule in the tuning file");
     if (!sched_valid(corr->precision, sched_index(t.schedule)))
         return set_error(SDC_ERR_UNSUPPORTED, "schedule not available for this precision");
@@ -251,6 +251,7 @@ sdc_status sdc_autotune_candidates(const sdc_bin_spec* bins, const sdc_corr_spec
     if (!bins || !corr || !n_out || (max_out > 0 && !out)) return sdc::set_error(SDC_ERR_INVALID_ARG, "null pointer");
     std::vector<int32_t> schedules = {SDC_SCHED_ONE_PASS, SDC_SCHED_LAG_SPLIT};
     if (split_precision(corr->precision)) schedules.push_back(SDC_SCHED_TWO_PASS);
+    if (corr->precision != SDC_PREC_FP32) schedules.push_back(SDC_SCHED_FOLD);
     std::vector<int32_t> segments;
     if (bins->kind == SDC_BINS_RADIAL) segments = {64, 256, sdc::kMaxSegmentPairs};
     else segments = {24, 48, 96, 192, 384};

@@ -56,9 +56,9 @@ class Tuning(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("segment_pairs", ctypes.c_int32)]
 
 
-SCHED_DEFAULT, SCHED_ONE_PASS, SCHED_TWO_PASS, SCHED_LAG_SPLIT = 0, 1, 2, 3
+SCHED_DEFAULT, SCHED_ONE_PASS, SCHED_TWO_PASS, SCHED_LAG_SPLIT, SCHED_FOLD = 0, 1, 2, 3, 4
 SCHEDULES = {"default": SCHED_DEFAULT, "one_pass": SCHED_ONE_PASS, "two_pass": SCHED_TWO_PASS,
-             "lag_split": SCHED_LAG_SPLIT}
+             "lag_split": SCHED_LAG_SPLIT, "fold": SCHED_FOLD}
 
 
 class SqSpec(ctypes.Structure):

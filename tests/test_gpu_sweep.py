@@ -23,7 +23,8 @@ def _tuning(rng, prec):
     """A random schedule the precision has (None = the plan's default) and a
     random segment length (None = default; short ones cut every stream into
     many tasks and merges)."""
-    scheds = [None, "one_pass", "lag_split"] + (["two_pass"] if prec in ("split_bf16", "split_fp16") else [])
+    scheds = ([None, "one_pass", "lag_split"] + (["two_pass"] if prec in ("split_bf16", "split_fp16") else [])
+              + (["fold"] if prec != "fp32" else []))
     segs = [None, 1, 3, 24]
     return scheds[int(rng.integers(0, len(scheds)))], segs[int(rng.integers(0, len(segs)))]
 

@@ -795,7 +795,8 @@ def _langevin(x):
     return 1.0 / np.tanh(x) - 1.0 / x
 
 
-def test_mc_independent_spins_field_and_anisotropy(orc):
+@pytest.mark.parametrize("site_order", [False, True])
+def test_mc_independent_spins_field_and_anisotropy(orc, site_order):
     """Spins without bonds in a field H_z and anisotropy A sample
     p(S_z) ~ exp((A S_z^2 + H_z S_z) / T) on the sphere (S_z uniform under the
     uniform measure): the mean and second moment of S_z over 20000 spins
@@ -807,7 +808,7 @@ def test_mc_independent_spins_field_and_anisotropy(orc):
     col = np.zeros(0, dtype=np.int32)
     init = inputs.random_unit_frames(1, n, seed=41)[0]
     S, acc, E, cone, Tl, ncol = orc.mc_anneal(row, col, np.zeros(0), init, 0x5DC0AA01, T, T, 0.9, 1, 300,
-                                              A=A, Hz=Hz)
+                                              A=A, Hz=Hz, site_order=site_order)
     assert ncol == 1 and Tl == T and acc.shape == (300,)
     w = lambda x: np.exp((A * x * x + Hz * x) / T)
     Z = quad(w, -1, 1)[0]
@@ -832,7 +833,8 @@ def _pairs(n_pairs, J, D=None):
     return row, col, Jv, Dv
 
 
-def test_mc_exchange_pairs(orc):
+@pytest.mark.parametrize("site_order", [False, True])
+def test_mc_exchange_pairs(orc, site_order):
     """Isolated bonds J S1.S2 at temperature T: the relative angle has
     p(cos g) ~ exp(-J cos g / T), so <S1.S2> = -L(J / T) with the Langevin
     function L(x) = coth x - 1/x; checked for both signs of J."""
@@ -840,7 +842,7 @@ def test_mc_exchange_pairs(orc):
     for J in (1.0, -1.3):
         row, col, Jv, _ = _pairs(n_pairs, J)
         init = inputs.random_unit_frames(1, 2 * n_pairs, seed=42)[0]
-        S, acc, E, *_ = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA02, T, T, 0.9, 1, 300)
+        S, acc, E, *_ = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA02, T, T, 0.9, 1, 300, site_order=site_order)
         dots = np.sum(S[0::2] * S[1::2], axis=1)
         ref = -_langevin(J / T)
         se = np.sqrt(np.var(dots) / n_pairs)
@@ -848,7 +850,8 @@ def test_mc_exchange_pairs(orc):
         np.testing.assert_allclose(E, J * dots.mean() / 2.0, rtol=1e-12)
 
 
-def test_mc_dmi_pairs(orc):
+@pytest.mark.parametrize("site_order", [False, True])
+def test_mc_dmi_pairs(orc, site_order):
     """Isolated bonds with only DMI, E = -D x.(S1 x S2): given S2 at angle t
     to x, S1 sees a field of size u = D sin t, so the pair's mean energy is
     the quadrature of -u L(u/T) weighted by sinh(u/T)/(u/T) over t."""
@@ -856,7 +859,7 @@ def test_mc_dmi_pairs(orc):
     n_pairs, T, D = 10000, 0.5, 1.2
     row, col, Jv, Dv = _pairs(n_pairs, 0.0, D)
     init = inputs.random_unit_frames(1, 2 * n_pairs, seed=43)[0]
-    S, acc, E, *_ = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA03, T, T, 0.9, 1, 300, D=Dv)
+    S, acc, E, *_ = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA03, T, T, 0.9, 1, 300, D=Dv, site_order=site_order)
     e = -D * np.cross(S[0::2], S[1::2])[:, 0]
     def weight(t):
         x = max(D * np.sin(t) / T, 1e-12)
@@ -870,7 +873,8 @@ def test_mc_dmi_pairs(orc):
     np.testing.assert_allclose(E, e.mean() / 2.0, rtol=1e-12)
 
 
-def test_mc_anneal_ferromagnet_ground_state(orc):
+@pytest.mark.parametrize("site_order", [False, True])
+def test_mc_anneal_ferromagnet_ground_state(orc, site_order):
     """Annealing an sc ferromagnet (J = -1) from T = 3 to 0.05 with T_{k+1} =
     0.9 T_k reaches the aligned state: E/N near -3 (3 bonds per site) and
     |M|/N near 1; the cone has shrunk and kept the acceptance near its
@@ -880,8 +884,8 @@ def test_mc_anneal_ferromagnet_ground_state(orc):
     row, col, Jv, _ = _nn_csr(pos, L, "sc", -1.0)
     init = inputs.random_unit_frames(1, pos.shape[0], seed=44)[0]
     S, acc, E, cone, Tl, ncol = orc.mc_anneal(row, col, Jv, init, 0x5DC0AA04, 3.0, 0.05, 0.9, 20, 100,
-                                              cone0=np.pi)
-    assert ncol == 2 and Tl == 0.05
+                                              cone0=np.pi, site_order=site_order)
+    assert ncol == (1 if site_order else 2) and Tl == 0.05
     assert -3.0 <= E < -2.9, E
     assert np.linalg.norm(S.sum(axis=0)) / pos.shape[0] > 0.97
     assert cone < 1.0
@@ -905,3 +909,19 @@ def test_mc_deterministic_and_schedule(orc):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     assert not np.array_equal(a[0], c[0])
     assert a[5] >= 3  # an odd periodic box has no two-colouring
+    # the plain site-order sweep: one class, a different chain of states
+    d = orc.mc_anneal(row, col, Jv, init, 7, 2.0, 0.5, 0.8, 3, 5, site_order=True)
+    assert d[5] == 1 and not np.array_equal(a[0], d[0])
+
+
+def test_mc_site_order_equals_colour_order_without_bonds(orc):
+    """Without bonds the greedy colouring has one class holding every site in
+    index order, so the colour-class sweep and the plain site-order sweep are
+    the same sweep, move for move."""
+    n = 500
+    row = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(0, dtype=np.int32)
+    init = inputs.random_unit_frames(1, n, seed=46)[0]
+    a = orc.mc_anneal(row, col, np.zeros(0), init, 11, 1.0, 1.0, 0.9, 1, 7, Hz=0.3)
+    b = orc.mc_anneal(row, col, np.zeros(0), init, 11, 1.0, 1.0, 0.9, 1, 7, Hz=0.3, site_order=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

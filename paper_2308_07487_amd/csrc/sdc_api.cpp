@@ -476,6 +476,11 @@ sdc_status sdc_plan_create_tuned(const float* positions_host, int64_t n_sites, c
         delete p;
         return set_err(SDC_ERR_UNSUPPORTED, "histogram window does not fit in LDS");
     }
+    if ((uint64_t)2 * L.n_pad * elem > (uint64_t)UINT32_MAX) {
+        // the fused kernel addresses two pack blocks with a 32-bit lane offset
+        delete p;
+        return set_err(SDC_ERR_UNSUPPORTED, "too many sites for the pack layout (two blocks must fit in 4 GiB)");
+    }
 
 #define TRY(x)                  \
     do {                        \

@@ -418,23 +418,71 @@ int fused_lds_bytes(int win, int precision) {
     return lag_group(precision) * win * (int)sizeof(double) + 1024 * (int)sizeof(float);
 }
 
+// MFMA instructions one stage_mma call issues per wave.
+template <int PREC, int PASS, int LW>
+constexpr int mfma_per_stage() {
+    if constexpr (PREC == SDC_PREC_FP32) return 8 * LW;
+    else if constexpr (PREC == SDC_PREC_BF16X3) return 6 * LW;
+    else if constexpr (PASS == kPassLarge) return LW;
+    else if constexpr (PASS == kPassSmall) return 2 * LW;
+    else return 3 * LW;
+}
+
+// Instruction order of one K-step for the schedules with a second
+// accumulator set (one-pass, lag-split): the next stage's loads first, then
+// each MFMA followed by up to NV vector instructions (the operand shuffles of
+// the following lags), so that the shuffles issue while the matrix core works
+// instead of in a burst in front of it (about 5% at the 36^3 workload).  The
+// two-pass and fold loops keep the compiler's order with the loads fenced
+// off from the MFMAs: there the interleave gains nothing (two-pass) or costs
+// register spills (fold, and the batch kernel).
+template <int NMF, int NV>
+__device__ __forceinline__ void interleave() {
+    __builtin_amdgcn_sched_group_barrier(0x020, 16, 0);  // vector memory reads
+#pragma unroll
+    for (int i = 0; i < NMF; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // vector ALU
+    }
+}
+
 // One K loop over all K-steps of a tile pair with NS register buffers: the
 // loads of the next NS - 1 K-steps are in flight while one step's MFMAs run
 // (load indices clamp to the last step, so the last round's extra loads are
-// harmless re-reads).  The scheduling barriers keep the loads ahead of the
-// MFMAs.
+// harmless re-reads).  For the interleaved schedules the main loop takes NS
+// steps per trip without a branch, so loads and MFMAs of a step share one
+// scheduling region, and the fewer than NS steps left after it (loaded
+// already) follow; the others skip the steps past the end inside the loop
+// and fence the loads off from the MFMAs.
 template <int PREC, int PASS, int SCHED, int NB, int LW, int OFF, int NS, class Load>
 __device__ __forceinline__ void k_loop(int nk, const Load& load, Acc<PREC, SCHED, LW>& acc) {
     Stage<PREC, NB> s[NS];
 #pragma unroll
     for (int j = 0; j < NS - 1; ++j) load(s[j], j);
-    for (int kk = 0; kk < nk; kk += NS) {
+    if constexpr (SCHED == kSchedOnePass || SCHED == kSchedLagSplit) {
+        constexpr int NMF = mfma_per_stage<PREC, PASS, LW>();
+        int kk = 0;
+        for (; kk + NS <= nk; kk += NS) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            load(s[(j + NS - 1) % NS], kk + j + NS - 1);
-            __builtin_amdgcn_sched_barrier(0);
-            if (j == 0 || kk + j < nk) stage_mma<PREC, PASS, SCHED, NB, LW, OFF>(s[j], acc);
-            __builtin_amdgcn_sched_barrier(0);
+            for (int j = 0; j < NS; ++j) {
+                load(s[(j + NS - 1) % NS], kk + j + NS - 1);
+                stage_mma<PREC, PASS, SCHED, NB, LW, OFF>(s[j], acc);
+                interleave<NMF, 4>();
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NS - 1; ++j)
+            if (kk + j < nk) stage_mma<PREC, PASS, SCHED, NB, LW, OFF>(s[j], acc);
+    } else {
+        for (int kk = 0; kk < nk; kk += NS) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                load(s[(j + NS - 1) % NS], kk + j + NS - 1);
+                __builtin_amdgcn_sched_barrier(0);
+                if (j == 0 || kk + j < nk) stage_mma<PREC, PASS, SCHED, NB, LW, OFF>(s[j], acc);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
 }
@@ -476,9 +524,14 @@ __device__ __forceinline__ void pair_loop(const TaskCtx& c) {
     const int dF = a.F8 - a.O8;  // B block of A block k (component c): k + c dF + ublk
     const int n_c = a.O8 / 2;    // PAIRED: K-steps per component
 
+    // lane byte offsets from a block's tile base: the site within the tile
+    // and, for the upper lane half, the next block (the plan keeps two pack
+    // blocks within 4 GiB)
+    const uint32_t offA = (uint32_t)(((int64_t)h * a.n_pad + wi * 32 + l32) * (int64_t)sizeof(Elem));
+    const uint32_t offB = (uint32_t)(((int64_t)h * a.n_pad + wj * 32 + l32) * (int64_t)sizeof(Elem));
+
     for (int p = c.st.p0; p < c.st.p1; ++p) {
         const KPair pr = a.pairs[p];
-        const int64_t si = (int64_t)pr.ti * kTile + wi * 32 + l32;
         const int64_t sj = (int64_t)pr.tj * kTile + wj * 32 + l32;
         Acc<PREC, SCHED, LW> acc;
 #pragma unroll
@@ -494,14 +547,22 @@ __device__ __forceinline__ void pair_loop(const TaskCtx& c) {
 
         // Register buffers: while K-step kk is multiplied the loads of later
         // steps are in flight (indices clamp to the last block).  Parts of
-        // an element a pass does not use are not loaded (dead loads).
+        // an element a pass does not use are not loaded (dead loads).  Each
+        // load is a uniform block address plus the lane's fixed byte offset.
+        const Elem* At = Ab + (int64_t)pr.ti * kTile;
+        const Elem* Bt = Bb + (int64_t)pr.tj * kTile;
         auto load = [&](Stage<PREC, NB>& b, int kk) {
             kk = kk < nk ? kk : nk - 1;
+            const int64_t np = a.n_pad;
+            // A block of lane half h: 2 kk + h (the zero block for the half
+            // past the last block)
+            const Elem* pa = At + (int64_t)(2 * kk) * np;
             const Elem* pb;
+            uint32_t ob = offB;
             if constexpr (PAIRED) {
-                const int alpha = kk / n_c, cc = kk - alpha * n_c;
-                b.a = Ab[(int64_t)(alpha * a.O8 + 2 * cc + h) * a.n_pad + si];
-                pb = Bb + (int64_t)(alpha * a.F8 + 2 * cc + h + ublk) * a.n_pad + sj;
+                // both halves in component alpha: B block 2 kk + h + alpha dF + ublk
+                const int alpha = (kk >= n_c) + (kk >= 2 * n_c);
+                pb = Bt + (int64_t)(2 * kk + alpha * dF + ublk) * np;
             } else {
                 // block indices of both lane halves from the step index
                 // (uniform); A: [3][O8] blocks flattened, then the zero block
@@ -509,11 +570,13 @@ __device__ __forceinline__ void pair_loop(const TaskCtx& c) {
                 const int k1 = k0 + 1 < nblk ? k0 + 1 : nblk - 1;
                 const int b0 = k0 + ((k0 >= a.O8) + (k0 >= 2 * a.O8)) * dF + ublk;
                 const int b1 = k1 + ((k1 >= a.O8) + (k1 >= 2 * a.O8)) * dF + ublk;
-                b.a = Ab[(int64_t)(k0 + h) * a.n_pad + si];
-                pb = Bb + (int64_t)(h ? b1 : b0) * a.n_pad + sj;
+                pb = Bt + (int64_t)b0 * np;
+                // offB holds one block for the upper half; it needs b1 - b0
+                ob += h ? (uint32_t)((int64_t)(b1 - b0 - 1) * np * (int64_t)sizeof(Elem)) : 0u;
             }
+            b.a = *(const Elem*)((const char*)pa + offA);
 #pragma unroll
-            for (int q = 0; q < NB; ++q) b.b[q] = pb[q * a.n_pad];
+            for (int q = 0; q < NB; ++q) b.b[q] = *(const Elem*)((const char*)(pb + q * np) + ob);
         };
 
         // Epilogue: bin of each accumulator element, LDS FP64 add per lag.

@@ -222,7 +222,9 @@ sdc_status sdc_plan_get_tuning(const sdc_plan* plan, sdc_tuning* tuning);
  *  best         : receives the winner;  best_ms : its median fused time
  *                 (milliseconds), or NULL;  candidate_ms : [n] medians of all
  *                 candidates in order, or NULL.
- * Synchronous; allocates and frees its own plans and spins.
+ * Synchronous; allocates and frees its own plans and spins.  With the
+ * environment variable SDC_TUNE_VERBOSE set (and not "0") every candidate's
+ * median is also printed to stderr as it is measured.
  * Errors: as sdc_plan_create; HIP; INVALID_ARG for a candidate with a zero
  * field or a file that cannot be written.
  */
@@ -301,6 +303,13 @@ sdc_status sdc_finalize(sdc_plan* plan, double* C_host, uint64_t* counts_host,
  *  Sqt_host : [n_q][n_lags][2] (re, im) or NULL.
  *  Sqw_host : [n_q][n_lags][2] (re, im) of sum_t w_t S(q,t) e^{-2 pi i k t/n_lags},
  *             or NULL (not both NULL).
+ * Accuracy: every bin carries the contraction's rounding.  Near q = 0 the
+ * sum runs over all N^2 pair elements, where unbiased rounding cancels and a
+ * one-signed residual does not: the reduced-precision forms keep one of at
+ * most 3e-10 (split-BF16, BF16x3) or 1e-9 (split-FP16) of the absolute pair
+ * mass sum_o A(o) A(o + t), A = sum_i |S_i| (the matrix cores' alignment of
+ * the products inside one instruction; measured 4.4e-11, 2.1e-11 and
+ * 2.7e-10 on a 36^3 antiferromagnet), FP32 below 1e-10.
  * Synchronises the stream; allocates and frees its own scratch.
  * Errors: INVALID_ARG, UNSUPPORTED (radial plan), STATE, OOM, HIP.
  */

@@ -308,6 +308,9 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
     }
     sdc_corr_spec c = *corr;
     c.flags |= SDC_FLAG_TIMING;
+    // SDC_TUNE_VERBOSE set and not "0": one stderr line per candidate timed
+    const char* env_verbose = std::getenv("SDC_TUNE_VERBOSE");
+    const bool verbose = env_verbose && *env_verbose && std::strcmp(env_verbose, "0") != 0;
     double best_t = 0.0;
     bool have = false;
     std::string summary;
@@ -336,6 +339,9 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
             std::sort(ms.begin(), ms.end());
             const double med = ms[ms.size() / 2];
             if (candidate_ms) candidate_ms[ci] = med;
+            if (verbose)
+                std::fprintf(stderr, "sdc_autotune: candidate %zu/%zu schedule %d segment %d: %.3f ms\n", ci + 1,
+                             cands.size(), (int)cand.schedule, (int)cand.segment_pairs, med);
             char buf[64];
             std::snprintf(buf, sizeof buf, "%s%d/%d:%.3f", summary.empty() ? "" : " ", (int)cand.schedule,
                           (int)cand.segment_pairs, med);

@@ -7,11 +7,13 @@ Every distinct size class (bin kind, size, K-steps, precision) of the
 workloads gets one sdc_autotune run on its first sample shape, with seeded
 unit spins: the single-sample workloads (sc 36^3 in split-BF16 and
 split-FP16, sc 32^3, sc 8^3, the 420^2 square lattice, the 65536-point
-ball) over all their lags and the built-in candidates; the 48 batch
-samples over their first --batch-lags lags with both schedules and three
-segment lengths (the batch runs them all in one launch, so their per-class
-choice matters less than the launch's schedule).  Each class's winner and
-every candidate's median time go to the file.
+ball) over all their lags, every schedule of the precision and the segment
+lengths 48, 96 and 192 (the ball: the built-in radial candidates); the 48
+batch samples over their first --batch-lags lags with the two-pass and
+lag-split schedules and the same segment lengths (the batch runs
+them all in one launch, so their per-class choice matters less than the
+launch's schedule).  Each class's winner and every candidate's median time
+go to the file.
 """
 from __future__ import annotations
 
@@ -53,18 +55,23 @@ def main():
     ap.add_argument("--batch-lags", type=int, default=64)
     args = ap.parse_args()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    os.environ["SDC_TUNE_VERBOSE"] = "1"  # the library prints each candidate's time as it is measured
     t_all = time.perf_counter()
     for label, pos, kind, spec, n_o, n_L, prec, full in shapes():
         if sdc.tuning_lookup(args.out, pos.shape[0], kind, n_o, n_L, prec, **spec) is not None:
             continue  # its size class is tuned already
         t0 = time.perf_counter()
-        if full:
+        if full and kind == sdc.BINS_RADIAL:
             best, ms, cands = sdc.autotune(pos, kind, n_o, n_L, prec, max_lags=0, cache_path=args.out, **spec)
+        elif full:
+            cands = [(sch, seg) for sch in ("one_pass", "two_pass", "lag_split", "fold") for seg in (48, 96, 192)]
+            best, ms, cands = sdc.autotune(pos, kind, n_o, n_L, prec, max_lags=0, candidates=cands,
+                                           cache_path=args.out, **spec)
         else:
-            cands = [(sch, seg) for sch in ("one_pass", "two_pass") for seg in (48, 96, 192)]
+            cands = [(sch, seg) for sch in ("two_pass", "lag_split") for seg in (48, 96, 192)]
             best, ms, cands = sdc.autotune(pos, kind, n_o, n_L, prec, max_lags=args.batch_lags, candidates=cands,
                                            cache_path=args.out, **spec)
-        times = " ".join(f"{c['schedule'][:3]}/{c['segment_pairs']}:{t:.2f}" for c, t in cands)
+        times = " ".join(f"{c['schedule'][:4]}/{c['segment_pairs']}:{t:.2f}" for c, t in cands)
         print(f"{label:18s} N={pos.shape[0]:7d} {n_o:4d}x{n_L:<4d} {prec:10s} -> {best['schedule']}/"
               f"{best['segment_pairs']} {ms:.2f} ms  [{times}]  ({time.perf_counter() - t0:.1f} s)", flush=True)
     print(f"tuning file {args.out} written in {time.perf_counter() - t_all:.1f} s", flush=True)

@@ -213,7 +213,7 @@ sdc_status sdc_plan_get_tuning(const sdc_plan* plan, sdc_tuning* tuning);
  * seeded uniform unit spins; the winner has the smallest median.
  *  candidates   : n_candidates tunings with every field set, or NULL for the
  *                 built-in list (sdc_autotune_candidates: every schedule the
- *                 precision has x segment lengths {24, 48, 96, 192, 384} for
+ *                 precision has x segment lengths {16, 32, 48, 96, 192} for
  *                 periodic kinds, {64, 256, all} for radial).
  *  cache_path   : JSON tuning file; when not NULL the winner is written under
  *                 the plan's size-class key with every candidate's time

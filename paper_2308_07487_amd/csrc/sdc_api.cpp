@@ -1018,12 +1018,43 @@ sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32
         delete b;
         return set_err(SDC_ERR_UNSUPPORTED, "too many fused tasks in the batch");
     }
+    // XCD queue ranges of about equal work, cut at stream boundaries (all
+    // lag groups of a stream segment in one queue).  Work of a stream's task:
+    // its tile pairs times (K-steps + 4), the 4 standing for the per-pair
+    // epilogue.
+    std::vector<int32_t> ranges(9, 0);
+    {
+        std::vector<int64_t> cut;     // task index at the end of every stream, in list order
+        std::vector<double> cum;      // work up to there
+        double w = 0.0;
+        for (int k = 0; k < n_plans; ++k) {
+            const sdc_plan* p = plans[order[k]];
+            for (size_t st = 0; st < p->lay.streams.size(); ++st) {
+                const KStream& ks = p->lay.streams[st];
+                w += (double)(ks.p1 - ks.p0) * (double)(p->nk + 4) * (double)args[k].n_groups;
+                cut.push_back(start[k] + (int64_t)(st + 1) * args[k].n_groups);
+                cum.push_back(w);
+            }
+        }
+        size_t c = 0;
+        for (int x = 1; x < 8; ++x) {
+            const double target = w * x / 8.0;
+            while (c < cum.size() && cum[c] < target) ++c;
+            // the stream end nearest to the target, never before the previous cut
+            int64_t r = c < cut.size() ? cut[c] : start[n_plans];
+            if (c > 0 && c < cum.size() && target - cum[c - 1] < cum[c] - target) r = cut[c - 1];
+            ranges[x] = (int32_t)std::max<int64_t>(r, ranges[x - 1]);
+        }
+        ranges[8] = (int32_t)start[n_plans];
+    }
     sdc::FusedArgs* d_args = nullptr;
     int64_t* d_start = nullptr;
     unsigned* d_queue = nullptr;
+    int32_t* d_ranges = nullptr;
     sdc_status s = dalloc(&d_args, args.size(), &b->owned);
     if (s == SDC_OK) s = dalloc(&d_start, start.size(), &b->owned);
     if (s == SDC_OK) s = dalloc(&d_queue, 8, &b->owned);
+    if (s == SDC_OK) s = dalloc(&d_ranges, 9, &b->owned);
     if (s != SDC_OK) {
         delete b;
         return s;
@@ -1031,6 +1062,7 @@ sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32
     hipError_t he = hipMemcpy(d_args, args.data(), args.size() * sizeof(sdc::FusedArgs), hipMemcpyHostToDevice);
     if (he == hipSuccess)
         he = hipMemcpy(d_start, start.data(), start.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(d_ranges, ranges.data(), 9 * sizeof(int32_t), hipMemcpyHostToDevice);
     if (he != hipSuccess) {
         delete b;
         return hip_err((int)he, "upload batch tables");
@@ -1040,6 +1072,7 @@ sdc_status sdc_batch_create_tuned(sdc_plan* const* plans, int32_t n_plans, int32
     bl.task_start = d_start;
     bl.n_plans = n_plans;
     bl.queue = d_queue;
+    bl.ranges = d_ranges;
     bl.total = (int)start[n_plans];
     bl.precision = prec;
     bl.radial = radial;

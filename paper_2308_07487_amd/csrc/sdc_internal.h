@@ -239,6 +239,7 @@ struct BatchLaunch {
     const int64_t* task_start;
     int n_plans;
     unsigned* queue;
+    const int32_t* ranges;  // [9]: XCD queue x holds tasks [ranges[x], ranges[x + 1])
     int total;
     int precision, radial, sched;
     int lds, grid;

@@ -734,17 +734,21 @@ __global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused
 
 // Persistent kernel over the tasks of several plans (one launch for a
 // batch of samples).  The global task list (plan-major, then stream, then
-// lag group) is cut into 8 contiguous ranges, one queue per XCD; a
-// workgroup takes tasks from its own XCD's queue with an atomic counter and,
-// once that queue is empty, from the following queues in turn.  Every
-// counter only grows and each queue is visited until it is found empty, so
-// every workgroup leaves the loop after at most total + 8 claims.  The
-// K-step addressing follows each plan's origin-block count (per component
-// when it is even).
+// lag group) is cut into 8 contiguous ranges of about equal work, at stream
+// boundaries, one queue per XCD; a workgroup takes tasks from its own XCD's
+// queue with an atomic counter and, once that queue is empty, from the
+// following queues in turn.  Equal work keeps the XCDs on their own queues
+// until the end, so the lag groups of a stream segment run on one XCD and
+// share its operands in L2 (ranges of equal task counts let the XCDs with
+// the small samples' short tasks steal the large samples' tasks for most of
+// the launch, and the operand fetches grew 8x).  Every counter only grows
+// and each queue is visited until it is found empty, so every workgroup
+// leaves the loop after at most total + 8 claims.  The K-step addressing
+// follows each plan's origin-block count (per component when it is even).
 template <int PREC, int RADIAL, int SCHED>
 __global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused_batch_kernel(
     const FusedArgs* __restrict__ args, const int64_t* __restrict__ task_start, int n_plans,
-    unsigned* __restrict__ queue, int per, int total) {
+    unsigned* __restrict__ queue, const int32_t* __restrict__ ranges, int total) {
     extern __shared__ double hist[];
     __shared__ int s_task, s_plan, s_queue, s_exhausted;
     if (threadIdx.x == 0) {
@@ -757,8 +761,8 @@ __global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused
             int x = s_queue, exhausted = s_exhausted;
             int t = -1;
             while (exhausted < 8) {
-                const int lo = x * per;
-                const int hi = min(lo + per, total);
+                const int lo = ranges[x];
+                const int hi = min(ranges[x + 1], total);
                 if (lo < hi) {
                     const unsigned k = atomicAdd(&queue[x], 1u);
                     if (k < (unsigned)(hi - lo)) {
@@ -878,13 +882,13 @@ int launch_fused_batch(const BatchLaunch& b, void* stream) {
     if (!fn) return (int)hipErrorInvalidValue;
     int e = launch_zero(b.queue, 8 * sizeof(unsigned), stream);
     if (e != 0) return e;
-    int per = (b.total + 7) / 8;
     const FusedArgs* args = b.args;
     const int64_t* task_start = b.task_start;
     int n_plans = b.n_plans;
     unsigned* queue = b.queue;
+    const int32_t* ranges = b.ranges;
     int total = b.total;
-    void* params[] = {(void*)&args, (void*)&task_start, (void*)&n_plans, (void*)&queue, (void*)&per,
+    void* params[] = {(void*)&args, (void*)&task_start, (void*)&n_plans, (void*)&queue, (void*)&ranges,
                       (void*)&total};
     return (int)hipLaunchKernel(fn, dim3(b.grid), dim3(threads_per_wg(b.sched)), params, b.lds,
                                 (hipStream_t)stream);

@@ -2,12 +2,16 @@
 //
 // What is tuned per size class (device architecture, bin kind,
 // floor(2 log2 N), K-steps, precision):
-//  - the schedule of the fused kernel (one K loop per tile pair at one
-//    workgroup per CU, or the two-pass form of the hi/lo splits at two), and
+//  - the schedule of the fused kernel (one-pass, two-pass, lag-split or
+//    fold; how the small split products are kept out of the large sums), and
 //  - the number of tile pairs per fused task (segment length): the tasks of
 //    one segment share a histogram and are merged into the global bins once;
-//    shorter segments keep the lag groups that run together in step on an
-//    XCD's L2, longer ones merge less.
+//    shorter segments keep the lag groups that run together on an XCD close
+//    enough in the pair list to share its L2, longer ones merge less.  The
+//    lag groups of a segment start as the XCD's workgroup slots free up, so
+//    unless their count divides the slots they drift apart by a fraction of
+//    the segment (on a bcc 40^3 sample with 19 lag groups: 1.8 TB fetched
+//    per launch with 16-pair segments, 12.3 TB with 96).
 // The tuner times every candidate on the device (HIP events around the
 // fused launch) and keeps the fastest; the results go to a small JSON file
 // that plan creation reads (SDC_TUNING_FILE).  The paper's CUTLASS variants
@@ -254,7 +258,7 @@ sdc_status sdc_autotune_candidates(const sdc_bin_spec* bins, const sdc_corr_spec
     if (corr->precision != SDC_PREC_FP32) schedules.push_back(SDC_SCHED_FOLD);
     std::vector<int32_t> segments;
     if (bins->kind == SDC_BINS_RADIAL) segments = {64, 256, sdc::kMaxSegmentPairs};
-    else segments = {24, 48, 96, 192, 384};
+    else segments = {16, 32, 48, 96, 192};
     int32_t n = 0;
     for (int32_t sch : schedules)
         for (int32_t seg : segments) {

@@ -1,19 +1,20 @@
 """Tunes the fused product for the benchmarked sample shapes on this GPU and
 writes the tuning file plan creation reads (SDC_TUNING_FILE).
 
-    python -m paper_2308_07487_amd.tune [--out FILE] [--batch-lags 64]
+    python -m paper_2308_07487_amd.tune [--out FILE] [--only all|full|batch] [--batch-lags 0]
 
 Every distinct size class (bin kind, size, K-steps, precision) of the
 workloads gets one sdc_autotune run on its first sample shape, with seeded
-unit spins: the single-sample workloads (sc 36^3 in split-BF16 and
-split-FP16, sc 32^3, sc 8^3, the 420^2 square lattice, the 65536-point
-ball) over all their lags, every schedule of the precision and the segment
-lengths 48, 96 and 192 (the ball: the built-in radial candidates); the 48
-batch samples over their first --batch-lags lags with the two-pass and
-lag-split schedules and the same segment lengths (the batch runs
-them all in one launch, so their per-class choice matters less than the
-launch's schedule).  Each class's winner and every candidate's median time
-go to the file.
+unit spins; classes already in the file are kept.  The single-sample
+workloads (sc 36^3 in split-BF16 and split-FP16, sc 32^3, sc 8^3, the 420^2
+square lattice, the 65536-point ball) run over all their lags with every
+schedule of the precision and the segment lengths 16, 32, 48 and 96 (the
+ball: the built-in radial candidates); the 48 batch samples with the
+two-pass schedule (the batch's work-weighted vote) and segments of 16, 32
+and 48 pairs, over all their lags by default (--batch-lags N: the first N;
+the segment choice depends on the number of lag groups that run together).
+Each class's winner and every candidate's median time go to the file, and
+the library prints every candidate's time as it is measured.
 """
 from __future__ import annotations
 
@@ -52,23 +53,26 @@ def shapes():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "tuning", "gfx950.json"))
-    ap.add_argument("--batch-lags", type=int, default=64)
+    ap.add_argument("--batch-lags", type=int, default=0, help="lags timed per batch sample (0: all)")
+    ap.add_argument("--only", default="all", choices=["all", "full", "batch"])
     args = ap.parse_args()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     os.environ["SDC_TUNE_VERBOSE"] = "1"  # the library prints each candidate's time as it is measured
     t_all = time.perf_counter()
     for label, pos, kind, spec, n_o, n_L, prec, full in shapes():
+        if (args.only == "full" and not full) or (args.only == "batch" and full):
+            continue
         if sdc.tuning_lookup(args.out, pos.shape[0], kind, n_o, n_L, prec, **spec) is not None:
             continue  # its size class is tuned already
         t0 = time.perf_counter()
         if full and kind == sdc.BINS_RADIAL:
             best, ms, cands = sdc.autotune(pos, kind, n_o, n_L, prec, max_lags=0, cache_path=args.out, **spec)
         elif full:
-            cands = [(sch, seg) for sch in ("one_pass", "two_pass", "lag_split", "fold") for seg in (48, 96, 192)]
+            cands = [(sch, seg) for sch in ("one_pass", "two_pass", "lag_split", "fold") for seg in (16, 32, 48, 96)]
             best, ms, cands = sdc.autotune(pos, kind, n_o, n_L, prec, max_lags=0, candidates=cands,
                                            cache_path=args.out, **spec)
         else:
-            cands = [(sch, seg) for sch in ("two_pass", "lag_split") for seg in (48, 96, 192)]
+            cands = [("two_pass", seg) for seg in (16, 32, 48)]
             best, ms, cands = sdc.autotune(pos, kind, n_o, n_L, prec, max_lags=args.batch_lags, candidates=cands,
                                            cache_path=args.out, **spec)
         times = " ".join(f"{c['schedule'][:4]}/{c['segment_pairs']}:{t:.2f}" for c, t in cands)

@@ -210,7 +210,9 @@ sdc_status sdc_plan_get_tuning(const sdc_plan* plan, sdc_tuning* tuning);
  * and returns the fastest.  Each candidate gets its own plan and runs one
  * warm-up and three timed accumulates (HIP events around the fused launch)
  * over the first min(n_lags, max_lags) lags (max_lags <= 0: all lags) on
- * seeded uniform unit spins; the winner has the smallest median.
+ * seeded uniform unit spins.  The winner: of the candidates whose median is
+ * within 0.5% of the smallest (ties within the timing noise), the one with
+ * the longest segment (fewest histogram merges), then the smallest median.
  *  candidates   : n_candidates tunings with every field set, or NULL for the
  *                 built-in list (sdc_autotune_candidates: every schedule the
  *                 precision has x segment lengths {16, 32, 48, 96, 192} for

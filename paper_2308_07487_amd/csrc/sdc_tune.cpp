@@ -315,8 +315,7 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
     // SDC_TUNE_VERBOSE set and not "0": one stderr line per candidate timed
     const char* env_verbose = std::getenv("SDC_TUNE_VERBOSE");
     const bool verbose = env_verbose && *env_verbose && std::strcmp(env_verbose, "0") != 0;
-    double best_t = 0.0;
-    bool have = false;
+    std::vector<double> meds(cands.size(), 0.0);
     std::string summary;
     for (size_t ci = 0; ci < cands.size(); ++ci) {
         {
@@ -350,14 +349,25 @@ sdc_status sdc_autotune(const float* positions_host, int64_t n_sites, const sdc_
             std::snprintf(buf, sizeof buf, "%s%d/%d:%.3f", summary.empty() ? "" : " ", (int)cand.schedule,
                           (int)cand.segment_pairs, med);
             summary += buf;
-            if (!have || med < best_t) {
-                best_t = med;
-                *best = cand;
-                have = true;
-            }
+            meds[ci] = med;
         }
     }
     (void)hipFree(spins);
+    // Candidates within 0.5% of the fastest are ties within the timing
+    // noise; of those the longest segment wins (fewer histogram merges, less
+    // write traffic), then the faster.
+    const double fastest = *std::min_element(meds.begin(), meds.end());
+    size_t pick = 0;
+    bool have = false;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        if (meds[ci] > fastest * 1.005) continue;
+        if (!have || cands[ci].segment_pairs > cands[pick].segment_pairs ||
+            (cands[ci].segment_pairs == cands[pick].segment_pairs && meds[ci] < meds[pick]))
+            pick = ci;
+        have = true;
+    }
+    *best = cands[pick];
+    const double best_t = meds[pick];
     if (best_ms) *best_ms = best_t;
     if (cache_path) {
         std::vector<TuneEntry> v = read_file(cache_path);

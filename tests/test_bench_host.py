@@ -46,3 +46,37 @@ def test_unknown_compare_precision_is_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2
     assert "--compare" in r.stderr
+
+
+def test_contraction_sum_against_brute_force():
+    """The summed-bin reference of each form (the exact sum of the piece
+    products the contraction keeps, plus the diagonal dropped ones) against a
+    plain loop over all ordered pairs; the pieces rebuild each value to the
+    form's precision (BF16x3 and FP32 exactly), and the splits' sum differs
+    from sum_o M.M by their dropped products."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(11)
+    f = torch.from_numpy(rng.standard_normal((7, 23, 3)).astype(np.float32))
+    n_o, n_L = 4, 4
+    M = f.double().sum(dim=1)
+    mm = np.array([float((M[:n_o] * M[t:t + n_o]).sum()) for t in range(n_L)])
+    for prec, rec_bar in (("fp32", 0.0), ("split_bf16", 2.0 ** -16), ("split_fp16", 2.0 ** -22), ("bf16x3", 0.0)):
+        ps = bench._pieces(torch, f, prec)
+        rec = sum(p.double() for p in ps)
+        assert float((rec - f.double()).abs().max()) <= rec_bar * float(f.abs().max())
+        kept, diag = bench._PIECE_PRODUCTS[prec]
+        P = [p.double().numpy() for p in ps]
+        brute = np.zeros(n_L)
+        for t in range(n_L):
+            for o in range(n_o):
+                for i in range(f.shape[1]):
+                    for j in range(f.shape[1]):
+                        for a, b in kept + (diag if i == j else []):
+                            brute[t] += P[a][o, i] @ P[b][o + t, j]
+        got = bench.contraction_sum(torch, f, prec, n_o, n_L)
+        np.testing.assert_allclose(got, brute, rtol=1e-13, atol=1e-12)
+        if prec == "fp32":
+            np.testing.assert_allclose(got, mm, rtol=1e-13)
+        else:
+            assert np.max(np.abs(got - mm)) > 0.0

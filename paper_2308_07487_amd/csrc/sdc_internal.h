@@ -55,6 +55,9 @@ constexpr int sched_index(int schedule) {
                                              : kSchedOnePass;
 }
 constexpr int wg_per_cu(int sched) { return sched == kSchedTwoPass || sched == kSchedFold ? 2 : 1; }
+// Waves per SIMD at that occupancy: the launch-bounds minimum that sets the
+// register budget (four SIMDs per CU, 64-lane waves).
+constexpr int waves_per_simd(int sched) { return wg_per_cu(sched) * threads_per_wg(sched) / 256; }
 constexpr bool sched_valid(int precision, int sched) {
     return sched == kSchedOnePass || sched == kSchedLagSplit ||
            (sched == kSchedTwoPass && (precision == SDC_PREC_SPLIT_BF16 || precision == SDC_PREC_SPLIT_FP16)) ||

@@ -718,7 +718,7 @@ __device__ __forceinline__ void fused_task(const FusedArgs& a, int task, double*
 }
 
 template <int PREC, int RADIAL, int PAIRED, int SCHED>
-__global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__(threads_per_wg(SCHED), waves_per_simd(SCHED)) void fused_kernel(FusedArgs a) {
     extern __shared__ double hist[];
     // XCD-aware task order: consecutive tasks land on the same XCD (work-
     // groups are dealt to the 8 XCDs round-robin), and consecutive tasks are
@@ -746,7 +746,7 @@ __global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused
 // leaves the loop after at most total + 8 claims.  The K-step addressing
 // follows each plan's origin-block count (per component when it is even).
 template <int PREC, int RADIAL, int SCHED>
-__global__ __launch_bounds__(threads_per_wg(SCHED), wg_per_cu(SCHED)) void fused_batch_kernel(
+__global__ __launch_bounds__(threads_per_wg(SCHED), waves_per_simd(SCHED)) void fused_batch_kernel(
     const FusedArgs* __restrict__ args, const int64_t* __restrict__ task_start, int n_plans,
     unsigned* __restrict__ queue, const int32_t* __restrict__ ranges, int total) {
     extern __shared__ double hist[];

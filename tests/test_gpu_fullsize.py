@@ -223,12 +223,12 @@ def test_sc36_structure_factor(sc36):
     assert np.max(np.abs(got[0].imag)) <= 1e-12 * np.max(scale)
 
 
-@pytest.mark.parametrize("prec,bar", [("split_fp16", 1e-6), ("split_bf16", 5e-5), ("bf16x3", 1e-6)])
+@pytest.mark.parametrize("prec,bar", [("split_fp16", 1e-6), ("split_bf16", 5e-5), ("bf16x3", 1e-6), ("fp32", 1e-6)])
 def test_sc32_fm_full(torch_dev, S, orc, prec, bar):
     """sc 32^3 ferromagnet from a z-aligned start (sigma = 0.3): spins stay
     nearly parallel, so split-BF16's rounding is coherent and only its
     deterministic bound 3 2^-16 (plus FP32 accumulation) applies; split-FP16
-    and the three-piece BF16 form meet 1e-6.  Every bin and lag against the
+    the three-piece BF16 form and FP32 meet 1e-6.  Every bin and lag against the
     FFT reference, and the summed-bin identity."""
     L, n_o, n_L = (32, 32, 32), 64, 256
     _say(f"sc 32^3 FM full size {prec}")
@@ -253,24 +253,35 @@ def test_sc32_fm_full(torch_dev, S, orc, prec, bar):
     assert e <= bar and s <= sbar
 
 
-def test_ball65k_radial_full(torch_dev, S, orc):
-    _say("ball of 65536 points, 1024 shells, full size split_bf16")
+@pytest.fixture(scope="module")
+def ball65k(torch_dev, S, orc):
+    """The radial workload's trajectory and the oracle's sampled shells
+    (shared by every precision)."""
     n, n_o, n_L, ns, rm = 65536, 64, 128, 1024, 50.0
     pos = inputs.ball_positions(n, 25.0, seed=0x5DC00013)
     fr = _traj(torch_dev, S, pos, S.BINS_RADIAL, (0, 0, 0), n_o + n_L - 1, J=1.0, dt=0.005,
                coupling=S.COUPLING_EXP_CUTOFF, r_cut=1.5, init=S.INIT_UNIFORM, seed=0x5DC00003)
-    H, counts, _ = _run_plan(S, pos, S.BINS_RADIAL, n_o, n_L, "split_bf16", fr, n_shells=ns, r_max=rm)
-    assert int(counts.sum()) == n * n
-    assert counts[0] >= n
-    s = _sum_err(H, _form_sum(torch_dev, fr, "split_bf16", n_o, n_L), _mm(torch_dev, fr, n_o, n_L))
     rng = np.random.default_rng(7)
     bins = np.unique(np.concatenate([[0, 1, 2, 100, 400, 700, 1000, ns - 1], rng.choice(ns, 8, replace=False)]))
     lags = [0, 1, n_L // 2, n_L - 1]
     Hs, cs = orc.binned_corr_select(pos, fr.cpu().numpy(), orc.RADIAL, n_o, lags, bins, n_shells=ns, r_max=rm)
-    np.testing.assert_array_equal(counts[bins], cs)
-    e = _normwise(H[np.asarray(lags)][:, bins], Hs)
-    sbar = _sum_bar("split_bf16", n, n_o)
-    print(f"  sampled normwise error {e:.3e}, summed-bin identity {s:.3e} (bar {sbar:.3g})", flush=True)
+    return dict(n=n, n_o=n_o, n_L=n_L, ns=ns, rm=rm, pos=pos, fr=fr, bins=bins, lags=lags, Hs=Hs, cs=cs,
+                mm=_mm(torch_dev, fr, n_o, n_L))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ball65k_radial_full(torch_dev, S, ball65k, prec):
+    b = ball65k
+    _say(f"ball of 65536 points, 1024 shells, full size {prec}")
+    n, n_o, n_L = b["n"], b["n_o"], b["n_L"]
+    H, counts, _ = _run_plan(S, b["pos"], S.BINS_RADIAL, n_o, n_L, prec, b["fr"], n_shells=b["ns"], r_max=b["rm"])
+    assert int(counts.sum()) == n * n
+    assert counts[0] >= n
+    np.testing.assert_array_equal(counts[b["bins"]], b["cs"])
+    s = _sum_err(H, _form_sum(torch_dev, b["fr"], prec, n_o, n_L), b["mm"])
+    e = _normwise(H[np.asarray(b["lags"])][:, b["bins"]], b["Hs"])
+    sbar = _sum_bar(prec, n, n_o)
+    print(f"  {prec}: sampled normwise error {e:.3e}, summed-bin identity {s:.3e} (bar {sbar:.3g})", flush=True)
     assert e <= BIN_BAR and s <= sbar
 
 
